@@ -1,0 +1,106 @@
+/* Plain FP64 CPU oracle for the batched perfectly-stirred-reactor (PSR)
+ * steady-state solve.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the independent reference the
+ * GPU library is checked against.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg may load it; the product path never does.  It
+ * shares no code, header or constant with the GPU library.
+ *
+ * What it computes (paper: Section 2, Eqs. 1-3; Section 3, Eqs. 4-9):
+ *   - species thermodynamics from single-range NASA-7 polynomials (the S and
+ *     H of Eq. 9),
+ *   - forward rate constants (Eq. 6), equilibrium constants (Eqs. 8-9),
+ *     reverse rate constants (Eq. 7), rates of progress (Eq. 5) and net
+ *     molar production rates (Eq. 4),
+ *   - the steady PSR residual from Eq. 2 (species) and Eq. 3 (energy),
+ *   - its analytic Jacobian (the paper uses finite differences; the analytic
+ *     form has the same root),
+ *   - a textbook partial-pivoting LU factorisation and solve,
+ *   - the hybrid damped-Newton / pseudo-transient solve of Section 3.
+ *
+ * Units: concentrations mol/cm^3, density g/cm^3, pressure Pa, energies
+ * J/mol, A in (cm^3/mol)^(order-1)/s, V = 1 cm^3.
+ */
+#ifndef PSR_ORACLE_H
+#define PSR_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int n_el, n_sp, n_rx;
+  const double *elem_w;  /* [E] g/mol                               */
+  const int *sp_el;      /* [N*E] atom counts                        */
+  const double *nasa;    /* [N*7] a1..a7, single range               */
+  const int *r_idx;      /* [I*3] reactant species, -1 = unused slot */
+  const int *r_nu;       /* [I*3] reactant coefficients              */
+  const int *p_idx;      /* [I*3] product species                    */
+  const int *p_nu;       /* [I*3] product coefficients               */
+  const double *A;       /* [I]                                      */
+  const double *beta;    /* [I]                                      */
+  const double *Ea;      /* [I] J/mol                                */
+  double *W;             /* [N] work: species weights, filled by om_prepare */
+} om_mech;
+
+typedef struct {
+  double P;          /* Pa                                  */
+  double tau;        /* residence time, s                   */
+  double T_in;       /* inlet temperature (isothermal: T)   */
+  const double *Y_in;/* [N] inlet mass fractions            */
+  int energy;        /* 0: isothermal, unknowns Y; 1: (Y, T) */
+} om_cond;
+
+typedef struct {
+  /* steady Newton attempt */
+  double rtol, atol_Y, atol_T; /* step-norm weights w = atol + rtol |x|        */
+  double ftol;                 /* scaled-residual bound for convergence        */
+  double lambda_min;           /* smallest damping factor tried                */
+  double T_min, T_max;         /* temperature bounds, K                        */
+  /* pseudo-transient (ROS2) conditioning */
+  double ts_rtol, ts_atol_Y, ts_atol_T; /* local-error weights                 */
+  double ts_neg_tol;           /* most negative mass fraction accepted         */
+  double h0, h_max;            /* first and largest step, in units of tau      */
+  double h_min;                /* smallest step before TS_FAILED, in seconds   */
+  double nw_h_ratio;           /* retry Newton only once h >= nw_h_ratio tau   */
+  int nw_max_it;               /* iterations per Newton attempt                */
+  int nw_every;                /* accepted steps between Newton attempts       */
+  int max_lin;                 /* total linear-solve budget                    */
+} om_opts;
+
+enum { OM_CONVERGED = 0, OM_MAXITER = 1, OM_TS_FAILED = 2, OM_NONFINITE = 3 };
+
+typedef struct {
+  int status;
+  int n_lin;      /* linear solves (residual + triangular solve pairs)      */
+  int n_jac;      /* Jacobian evaluations + factorisations                  */
+  int n_ts;       /* accepted pseudo-transient steps                        */
+  int n_attempts; /* Newton attempts started                                */
+  double sres;    /* scaled residual at the converged base point            */
+} om_stats;
+
+void om_prepare(om_mech *m);
+void om_default_opts(om_opts *o);
+int om_n_unknowns(const om_mech *m, int energy);
+
+void om_thermo(const om_mech *m, double T, double *cp_R, double *h_RT, double *s_R);
+void om_rate_constants(const om_mech *m, double T, double *kf, double *Kc, double *kr);
+void om_production(const om_mech *m, double T, double P, const double *Y,
+                   double *C, double *q, double *wdot);
+void om_residual(const om_mech *m, const om_cond *c, const double *x, double *F);
+double om_scaled_residual(const om_mech *m, const om_cond *c, const double *x);
+void om_jacobian(const om_mech *m, const om_cond *c, const double *x, double *J);
+void om_jacobian_complex_step(const om_mech *m, const om_cond *c, const double *x, double *J);
+void om_mass_diag(const om_mech *m, const om_cond *c, const double *x, double *M);
+
+int om_lu_factor(int n, double *a, int *piv);
+void om_lu_solve(int n, const double *lu, const int *piv, double *b);
+
+int om_solve(const om_mech *m, const om_cond *c, const om_opts *o, double *x, om_stats *st);
+int om_time_march_only(const om_mech *m, const om_cond *c, const om_opts *o, double *x,
+                       int max_steps, om_stats *st);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,11 @@
+"""Seeded synthetic inputs shared by the oracle tests and the GPU path.
+
+Holds no solver arithmetic: it draws mechanisms, reactor conditions and
+initial guesses, nothing else.
+"""
+from .conditions import initial_guess, make_conditions
+from .configs import WORKLOADS, mechanism, subset, workload
+from .mechanism import make_mechanism, species_weights
+
+__all__ = ["make_mechanism", "species_weights", "make_conditions", "initial_guess",
+           "WORKLOADS", "mechanism", "workload", "subset"]

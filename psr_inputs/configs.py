@@ -1,0 +1,68 @@
+"""The five synthetic workloads and their seeds.
+
+| name        | mechanism (N/I)              | B      | energy | T / T_in      | tau range     | inlet |
+|-------------|------------------------------|--------|--------|---------------|---------------|-------|
+| isothermal  | 10/20                        | 16     | no     | 1500 K fixed  | 1e-4..1e-1 s  | Dirichlet(1) |
+| energy      | 53/325                       | 4096   | yes    | U[300,800] K  | 1e-5..1e-1 s  | phi U[0.5,2.5] |
+| mixed       | 53/325 (same mechanism)      | 16384  | yes    | as energy     | as energy     | as energy (first 4096 identical) |
+| uneven      | 30/200, 100/600, 200/1200    | 65536  | yes    | U[300,800] K  | 1e-6..1 s     | phi U[0.5,2.5] |
+| soot        | 150/900 + 6 moments          | 8192   | yes    | U[300,800] K  | 1e-3..1e-1 s  | phi U[1.5,3] |
+
+Pressure is 1 atm everywhere (the paper's runs are at 1 atm, Sections 5-6).
+"""
+from __future__ import annotations
+
+from functools import lru_cache
+
+import numpy as np
+
+from .conditions import initial_guess, make_conditions
+from .mechanism import make_mechanism
+
+MECH_SPECS = {
+    "isothermal": (10, 20, 11),
+    "energy": (53, 325, 21),
+    "mixed": (53, 325, 21),
+    "uneven_a": (30, 200, 41),
+    "uneven_b": (100, 600, 42),
+    "uneven_c": (200, 1200, 43),
+}
+
+WORKLOADS = {
+    "isothermal": dict(mech="isothermal", B=16, seed=12, energy=False, recipe="dirichlet",
+                       tau_range=(1e-4, 1e-1), T_in=1500.0),
+    "energy": dict(mech="energy", B=4096, B_draw=16384, seed=22, energy=True, recipe="phi",
+                   tau_range=(1e-5, 1e-1)),
+    "mixed": dict(mech="mixed", B=16384, seed=22, energy=True, recipe="phi",
+                  tau_range=(1e-5, 1e-1)),
+}
+
+
+@lru_cache(maxsize=None)
+def mechanism(name: str) -> dict:
+    n_sp, n_rx, seed = MECH_SPECS[name]
+    return make_mechanism(n_sp, n_rx, seed)
+
+
+def workload(name: str, n_reactors: int | None = None):
+    """(mechanism, conditions, x0, energy) for a named workload.
+
+    The conditions are always drawn at the workload's full draw size and then
+    truncated, so `n_reactors` gives a prefix of the full batch, and the
+    'energy' workload is the first 4096 reactors of the 'mixed' one.
+    """
+    spec = WORKLOADS[name]
+    mech = mechanism(spec["mech"])
+    B = spec["B"] if n_reactors is None else int(n_reactors)
+    cond = make_conditions(mech, spec.get("B_draw", spec["B"]), spec["seed"],
+                           recipe=spec["recipe"], tau_range=spec["tau_range"],
+                           T_in=spec.get("T_in"))
+    cond = {k: np.ascontiguousarray(v[..., :B]) for k, v in cond.items()}
+    x0 = initial_guess(cond, spec["energy"])
+    return mech, cond, x0, spec["energy"]
+
+
+def subset(cond: dict, x0: np.ndarray, idx) -> tuple[dict, np.ndarray]:
+    idx = np.asarray(idx)
+    return ({k: np.ascontiguousarray(v[..., idx]) for k, v in cond.items()},
+            np.ascontiguousarray(x0[:, idx]))
