@@ -1,0 +1,185 @@
+/* psr.h - C ABI of the MI355X (gfx950) batched perfectly-stirred-reactor solver.
+ *
+ * The library solves, for many independent reactors at once, the steady
+ * state of the PSR species and energy balances (paper: Section 2, Eqs. 1-3)
+ * with mass-action kinetics (Section 3, Eqs. 4-9), by the hybrid Newton /
+ * pseudo-transient method of Section 3.  All compute runs in hand-written
+ * HIP kernels; this header uses plain C types only.
+ *
+ * Conventions
+ *   - Every function returns psr_status; PSR_OK is 0.  Nothing throws across
+ *     the ABI.  On a non-OK status psr_last_error() returns a message
+ *     (thread-local, valid until the next call on that thread).
+ *   - "device pointer" means memory allocated on the current HIP device
+ *     (e.g. a torch tensor's data_ptr()); "host pointer" means CPU memory.
+ *     The caller owns every array it passes; the library keeps no pointer to
+ *     caller memory after a call returns, except that launches on `stream`
+ *     may still be running after an asynchronous call returns.
+ *   - `stream` is a hipStream_t passed as void*; NULL is the null stream.
+ *   - Batch arrays use the structure-of-arrays layout [var][reactor]:
+ *     element (i, b) of an [n][B] array is at index i*B + b.
+ *   - Units: P in Pa, tau in s, T in K, mass fractions dimensionless,
+ *     A in (cm^3/mol)^(order-1)/s, E in J/mol, NASA-7 coefficients for
+ *     c_p/R, H/RT, S/R.  Concentrations are mol/cm^3; the reactor volume is
+ *     1 cm^3 (it cancels from the steady state).
+ */
+#ifndef PSR_H
+#define PSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PSR_OK = 0,
+  PSR_EINVAL = 1,       /* invalid argument or mechanism                    */
+  PSR_ENOMEM = 2,       /* device allocation failed / workspace too small    */
+  PSR_EDEVICE = 3,      /* a HIP call failed                                 */
+  PSR_EUNSUPPORTED = 4  /* valid request outside what this build supports    */
+} psr_status;
+
+/* Per-reactor outcome written to psr_group.status. */
+enum {
+  PSR_R_CONVERGED = 0, /* root found: weighted Newton step <= 1 and scaled residual <= ftol */
+  PSR_R_MAXITER = 1,   /* linear-solve budget spent                                         */
+  PSR_R_TS_FAILED = 2, /* pseudo-transient step size fell below h_min                        */
+  PSR_R_NONFINITE = 3  /* converged iterate not finite                                       */
+};
+
+enum { PSR_FP64 = 0, PSR_MIXED = 1 };        /* precision of the LU factorisation */
+enum { PSR_PLAIN = 0, PSR_PERSISTENT = 1 };  /* scheduler                          */
+
+typedef struct psr_mech *psr_mech_t; /* opaque; immutable after creation */
+
+/* Mechanism description (host pointers, copied at creation).
+ * Reactions are elementary and reversible (Eqs. 4-7): up to three distinct
+ * reactant species and three distinct product species, each with a positive
+ * integer coefficient; index -1 marks an unused slot.                       */
+typedef struct {
+  int32_t n_elements, n_species, n_reactions;
+  const double *elem_weight;     /* [E] g/mol                                  */
+  const int32_t *species_elems;  /* [N][E] atom counts; W_i = sum_e a_ie W_e   */
+  const double *nasa7;           /* [N][7] a1..a7, single range                */
+  double t_low, t_high;          /* validity range of the polynomials, K       */
+  const int32_t *reac_idx;       /* [I][3] reactant species or -1              */
+  const int32_t *reac_nu;        /* [I][3] reactant coefficients (>= 1)        */
+  const int32_t *prod_idx;       /* [I][3] product species or -1               */
+  const int32_t *prod_nu;        /* [I][3] product coefficients (>= 1)         */
+  const double *A;               /* [I] pre-exponential factor (Eq. 6)         */
+  const double *beta;            /* [I] temperature exponent (Eq. 6)           */
+  const double *Ea;              /* [I] activation energy, J/mol (Eq. 6)       */
+} psr_mech_desc;
+
+/* Validate and upload a mechanism to the current device.
+ * Checks: counts positive, indices in range, coefficients >= 1, no species
+ * on both sides of a reaction, every reaction balanced in every element,
+ * positive species weights, t_low < t_high.  Errors: PSR_EINVAL (with the
+ * offending reaction or species in psr_last_error), PSR_EDEVICE. */
+psr_status psr_create_mechanism(const psr_mech_desc *desc, psr_mech_t *out);
+psr_status psr_destroy_mechanism(psr_mech_t mech);
+
+/* Number of unknowns per reactor: N (isothermal) or N + 1 (energy). */
+int32_t psr_num_unknowns(psr_mech_t mech, int32_t energy);
+
+/* Reactor conditions: device pointers, [B] or [N][B]. */
+typedef struct {
+  int64_t n_reactors;  /* B >= 1                                               */
+  int32_t energy;      /* 0: isothermal at T = T_in, unknowns Y; 1: unknowns (Y, T) */
+  const double *P;     /* [B] pressure, Pa                                     */
+  const double *tau;   /* [B] residence time, s                                */
+  const double *T_in;  /* [B] inlet temperature (isothermal: reactor T), K     */
+  const double *Y_in;  /* [N][B] inlet mass fractions                          */
+} psr_conditions;
+
+/* Steady PSR residual F(x) (Eq. 2 and Eq. 3 multiplied by -rho V):
+ *   F_i = mdot (Y_i - Y_in,i) - V W_i wdot_i,   mdot = rho V / tau
+ *   F_T = mdot sum_i Y_in,i (h_i(T) - h_i(T_in)) + V sum_i H_i(T) wdot_i
+ * with wdot from Eqs. 4-9.  x, F: device [n][B].  scaled: optional device
+ * [B], each reactor's residual relative to the magnitudes of the terms that
+ * make it up (max over equations).  Asynchronous on `stream`.             */
+psr_status psr_residual(psr_mech_t mech, const psr_conditions *cond, const double *x, double *F,
+                        double *scaled, void *stream);
+
+/* Analytic Jacobian dF/dx of psr_residual at x.  J: device [B][n][n],
+ * row-major per reactor (J[b*n*n + r*n + c] = dF_r/dx_c).  Asynchronous. */
+psr_status psr_jacobian(psr_mech_t mech, const psr_conditions *cond, const double *x, double *J,
+                        void *stream);
+
+/* Batched LU with partial pivoting of B independent n x n row-major
+ * matrices (device [B][n][n], overwritten by L\U with unit-lower L), pivots
+ * device [B][n] (LAPACK convention: row k was swapped with row piv[k]),
+ * info device [B] (0, or k+1 if column k had no nonzero pivot).
+ * precision PSR_FP64 factors in double; PSR_MIXED rounds each matrix to
+ * float, factors in float and writes the float factors back as double.
+ * Asynchronous.                                                             */
+psr_status psr_lu_factor_batch(int32_t n, int64_t batch, int32_t precision, double *A, int32_t *piv,
+                               int32_t *info, void *stream);
+
+/* Solve with the factors of psr_lu_factor_batch: b (device [B][n]) is
+ * overwritten with the solution.  Asynchronous.                            */
+psr_status psr_lu_solve_batch(int32_t n, int64_t batch, const double *LU, const int32_t *piv,
+                              double *b, void *stream);
+
+typedef struct {
+  int32_t precision;  /* PSR_FP64 or PSR_MIXED                              */
+  int32_t scheduler;  /* PSR_PLAIN or PSR_PERSISTENT                        */
+  /* steady Newton attempt */
+  double rtol, atol_Y, atol_T; /* step-norm weights w = atol + rtol |x|         */
+  double ftol;                 /* scaled-residual bound for convergence         */
+  double lambda_min;           /* smallest damping factor tried                 */
+  double T_min, T_max;         /* temperature bounds, K                         */
+  /* pseudo-transient (ROS2) conditioning */
+  double ts_rtol, ts_atol_Y, ts_atol_T; /* local-error weights                  */
+  double ts_neg_tol;           /* most negative mass fraction accepted          */
+  double h0, h_max;            /* first and largest step, in units of tau       */
+  double h_min;                /* smallest step before TS_FAILED, s             */
+  double nw_h_ratio;           /* retry Newton only once h >= nw_h_ratio * tau  */
+  int32_t nw_max_it;           /* iterations per Newton attempt                 */
+  int32_t nw_every;            /* accepted steps between Newton attempts        */
+  int32_t max_lin;             /* per-reactor linear-solve budget               */
+  /* mixed precision */
+  int32_t max_refine;          /* refinement sweeps per solve before FP64 fallback */
+} psr_solve_opts;
+
+/* Fill opts with the defaults (FP64, plain scheduler, tolerances above). */
+void psr_default_opts(psr_solve_opts *opts);
+
+/* One mechanism's reactors in a solve.  Device pointers. */
+typedef struct {
+  psr_mech_t mech;
+  psr_conditions cond;
+  double *x_inout;   /* [n][B] initial guess in, result out            */
+  int32_t *status;   /* [B] PSR_R_* per reactor                         */
+  int32_t *n_lin;    /* [B] linear solves used per reactor (may be NULL) */
+} psr_group;
+
+typedef struct {
+  int64_t reactors, converged;
+  int64_t lin_total, lin_max;   /* linear solves summed / worst reactor       */
+  int64_t jac_total;            /* Jacobian evaluations + factorisations      */
+  int64_t fp64_fallbacks;       /* mixed mode: matrices refactored in FP64    */
+  int32_t rounds;               /* plain scheduler: host-driven rounds        */
+  double kernel_ms;             /* device time of the solve, from HIP events  */
+} psr_solve_stats;
+
+/* Workspace (device bytes) psr_solve_batch needs for these groups/opts. */
+size_t psr_workspace_bytes(const psr_group *groups, int32_t n_groups, const psr_solve_opts *opts);
+
+/* Solve every reactor of every group.  workspace: device buffer of at
+ * least psr_workspace_bytes() bytes (else PSR_ENOMEM).  Blocks until the
+ * solve is complete on `stream`.  A reactor that does not converge is not an
+ * API error: its status says why.  stats (host, optional) receives totals. */
+psr_status psr_solve_batch(const psr_group *groups, int32_t n_groups, const psr_solve_opts *opts,
+                           void *workspace, size_t workspace_bytes, psr_solve_stats *stats,
+                           void *stream);
+
+/* Message for the last non-OK status on this thread ("" if none). */
+const char *psr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

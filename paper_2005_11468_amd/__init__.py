@@ -1,0 +1,186 @@
+"""MI355X (gfx950) batched perfectly-stirred-reactor steady-state solver.
+
+Thin Python binding over the C ABI of libpsr.so (include/psr.h): the
+functions below only marshal torch device tensors into pointers; every step
+of the solve runs in the library's HIP kernels.  There is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import (PSR_FP64, PSR_MIXED, PSR_PERSISTENT, PSR_PLAIN, STATUS_NAMES, PSRError,
+                   SolveOpts, SolveStats)
+
+__all__ = ["Mechanism", "residual", "jacobian", "lu_factor_batch", "lu_solve_batch",
+           "solve_batch", "default_opts", "workspace_bytes", "PSR_FP64", "PSR_MIXED",
+           "PSR_PLAIN", "PSR_PERSISTENT", "STATUS_NAMES", "PSRError"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _dev_f64(t, name):
+    torch = _torch()
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+            and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float64 device tensor")
+    return t
+
+
+class Mechanism:
+    """A mechanism uploaded with psr_create_mechanism (host arrays copied)."""
+
+    def __init__(self, mech: dict):
+        L = _lib.load()
+        f64 = lambda k: np.ascontiguousarray(mech[k], dtype=np.float64)
+        i32 = lambda k: np.ascontiguousarray(mech[k], dtype=np.int32)
+        self._arrays = dict(ew=f64("elem_weight"), se=i32("species_elems"), nasa=f64("nasa7"),
+                            ri=i32("reac_idx"), rn=i32("reac_nu"), pi=i32("prod_idx"),
+                            pn=i32("prod_nu"), A=f64("A"), beta=f64("beta"), Ea=f64("Ea"))
+        a = self._arrays
+        self.n_species = a["se"].shape[0]
+        self.n_reactions = a["ri"].shape[0]
+        dpp = lambda x: x.ctypes.data_as(_lib.dp)
+        ipp = lambda x: x.ctypes.data_as(_lib.ip)
+        desc = _lib.MechDesc(a["se"].shape[1], self.n_species, self.n_reactions, dpp(a["ew"]),
+                             ipp(a["se"]), dpp(a["nasa"]), float(mech.get("t_low", 300.0)),
+                             float(mech.get("t_high", 3000.0)), ipp(a["ri"]), ipp(a["rn"]),
+                             ipp(a["pi"]), ipp(a["pn"]), dpp(a["A"]), dpp(a["beta"]), dpp(a["Ea"]))
+        h = C.c_void_p()
+        _lib.check(L.psr_create_mechanism(C.byref(desc), C.byref(h)), "psr_create_mechanism")
+        self.handle = h
+
+    def n_unknowns(self, energy: bool) -> int:
+        return int(_lib.load().psr_num_unknowns(self.handle, 1 if energy else 0))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib._lib is not None:
+            _lib._lib.psr_destroy_mechanism(h)
+            self.handle = None
+
+
+def _conditions(cond: dict, energy: bool):
+    P = _dev_f64(cond["P"], "P")
+    tau = _dev_f64(cond["tau"], "tau")
+    Tin = _dev_f64(cond["T_in"], "T_in")
+    Yin = _dev_f64(cond["Y_in"], "Y_in")
+    B = P.shape[0]
+    if tau.shape[0] != B or Tin.shape[0] != B or Yin.shape[1] != B:
+        raise ValueError("condition arrays disagree on the batch size")
+    return _lib.Conditions(B, 1 if energy else 0, _ptr(P), _ptr(tau), _ptr(Tin), _ptr(Yin))
+
+
+def residual(mech: Mechanism, cond: dict, energy: bool, x, F=None, scaled=None, stream=None):
+    """psr_residual: F(x) for every reactor; x, F are [n][B] float64 device tensors."""
+    torch = _torch()
+    c = _conditions(cond, energy)
+    x = _dev_f64(x, "x")
+    if F is None:
+        F = torch.empty_like(x)
+    st = _lib.load().psr_residual(mech.handle, C.byref(c), _ptr(x), _ptr(F),
+                                  _ptr(scaled) if scaled is not None else None, _stream(stream))
+    _lib.check(st, "psr_residual")
+    return F
+
+
+def jacobian(mech: Mechanism, cond: dict, energy: bool, x, J=None, stream=None):
+    """psr_jacobian: dF/dx, [B][n][n] row-major per reactor."""
+    torch = _torch()
+    c = _conditions(cond, energy)
+    x = _dev_f64(x, "x")
+    n, B = x.shape
+    if J is None:
+        J = torch.empty((B, n, n), dtype=torch.float64, device=x.device)
+    _lib.check(_lib.load().psr_jacobian(mech.handle, C.byref(c), _ptr(x), _ptr(J), _stream(stream)),
+               "psr_jacobian")
+    return J
+
+
+def lu_factor_batch(A, precision=PSR_FP64, stream=None):
+    """psr_lu_factor_batch on a [B][n][n] float64 tensor (in place).  Returns (A, piv, info)."""
+    torch = _torch()
+    A = _dev_f64(A, "A")
+    B, n, _ = A.shape
+    piv = torch.empty((B, n), dtype=torch.int32, device=A.device)
+    info = torch.empty((B,), dtype=torch.int32, device=A.device)
+    _lib.check(_lib.load().psr_lu_factor_batch(n, B, precision, _ptr(A), _ptr(piv), _ptr(info),
+                                               _stream(stream)), "psr_lu_factor_batch")
+    return A, piv, info
+
+
+def lu_solve_batch(LU, piv, b, stream=None):
+    """psr_lu_solve_batch: b ([B][n] float64) overwritten with the solutions."""
+    LU = _dev_f64(LU, "LU")
+    b = _dev_f64(b, "b")
+    B, n, _ = LU.shape
+    _lib.check(_lib.load().psr_lu_solve_batch(n, B, _ptr(LU), _ptr(piv.contiguous()), _ptr(b),
+                                              _stream(stream)), "psr_lu_solve_batch")
+    return b
+
+
+def default_opts(**overrides) -> SolveOpts:
+    o = SolveOpts()
+    _lib.load().psr_default_opts(C.byref(o))
+    for k, v in overrides.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+class _Groups:
+    def __init__(self, groups):
+        self.keep = []
+        arr = (_lib.Group * len(groups))()
+        for i, g in enumerate(groups):
+            c = _conditions(g["cond"], g["energy"])
+            x = _dev_f64(g["x"], "x")
+            st = g["status"]
+            nl = g.get("n_lin")
+            arr[i] = _lib.Group(g["mech"].handle, c, _ptr(x), _ptr(st),
+                                _ptr(nl) if nl is not None else None)
+            self.keep.append(g)
+        self.arr = arr
+        self.n = len(groups)
+
+
+def workspace_bytes(groups, opts: SolveOpts) -> int:
+    G = _Groups(groups)
+    return int(_lib.load().psr_workspace_bytes(G.arr, G.n, C.byref(opts)))
+
+
+def solve_batch(groups, opts: SolveOpts | None = None, workspace=None, stats: bool = True,
+                stream=None):
+    """psr_solve_batch.  groups: list of dicts with keys mech, cond (device
+    tensors), energy, x ([n][B] float64, in/out), status ([B] int32), n_lin
+    ([B] int32, optional).  Returns (SolveStats or None, workspace tensor)."""
+    torch = _torch()
+    opts = opts or default_opts()
+    G = _Groups(groups)
+    L = _lib.load()
+    need = int(L.psr_workspace_bytes(G.arr, G.n, C.byref(opts)))
+    dev = groups[0]["x"].device
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty((max(need, 1),), dtype=torch.uint8, device=dev)
+    st = SolveStats() if stats else None
+    r = L.psr_solve_batch(G.arr, G.n, C.byref(opts), _ptr(workspace), workspace.numel(),
+                          C.byref(st) if st is not None else None, _stream(stream))
+    _lib.check(r, "psr_solve_batch")
+    return st, workspace

@@ -1,0 +1,468 @@
+// Device building blocks of the batched PSR solver (gfx950).
+//
+// One workgroup of BS threads owns one reactor at a time.  Every per-reactor
+// array lives in LDS (or, for the host-driven scheduler, in global memory
+// reached through the same flat pointers).  Threads stride over species,
+// reactions, matrix rows and elements; block reductions broadcast scalars.
+//
+// Paper: Section 2 (Eqs. 1-3, the PSR balances), Section 3 (Eqs. 4-9, the
+// rates and the hybrid Newton / time-integration method).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace psr {
+
+constexpr double kR = 8.314462618;  // J/(mol K)
+constexpr double kPatm = 101325.0;  // Pa, standard state of Eq. 8
+constexpr double kV = 1.0;          // cm^3
+constexpr double kGamma = 1.7071067811865475244;  // ROS2: 1 + 1/sqrt(2)
+
+// Mechanism tables in device memory (by value in kernel arguments).
+struct MechDev {
+  int N, I, nnz;
+  const double *W;     // [N] g/mol
+  const double *nasa;  // [N*7]
+  const double *lnA, *beta, *EoR;  // [I]; E/R in K
+  const int *dnu;                  // [I] sum of net coefficients
+  const int *r_idx, *r_nu, *p_idx, *p_nu;  // [I*3], -1 pads
+  const int *sp_ptr, *sp_rx, *sp_nu;       // species -> (reaction, net nu), CSR
+};
+
+struct Opts {
+  int precision, scheduler;
+  double rtol, atol_Y, atol_T, ftol, lambda_min, T_min, T_max;
+  double ts_rtol, ts_atol_Y, ts_atol_T, ts_neg_tol, h0, h_max, h_min, nw_h_ratio;
+  int nw_max_it, nw_every, max_lin, max_refine;
+};
+
+enum Phase : int { PH_NW_BASE = 0, PH_NW_TRIAL = 1, PH_TS1 = 2, PH_TS2 = 3, PH_DONE = 4 };
+enum RStatus : int { RS_CONVERGED = 0, RS_MAXITER = 1, RS_TS_FAILED = 2, RS_NONFINITE = 3, RS_RUNNING = 9 };
+
+// Per-reactor controller state of the hybrid method.
+struct RState {
+  int phase, status, n_lin, n_jac, n_ts, n_att, nw_it, accepted;
+  int fb64;      // mixed mode: current matrix refactored in FP64
+  int n_fb64;    // mixed mode: FP64 fallbacks so far
+  int sing, fin; // matrix flags of this round
+  double nd, lam, h, sres;
+};
+
+// LDS / workspace layout of one reactor, in doubles (8-byte units).  The
+// first `persist` doubles (inlet data, vectors, matrices, pivots) carry the
+// controller's state from one round to the next; the rest is scratch that
+// every residual evaluation rebuilds.
+struct Layout {
+  int N, I, n, lda;
+  int Yin, Hin;                                       // inlet data
+  int x, xnw, xev, d, t, M, G, rs, cs, rb, rr;        // vectors
+  int A64, A32, piv, persist;                         // matrices
+  int C, hRT, sR, cpR, wdot, gross, Erow, dwdT;       // species scratch
+  int kf, kr, Rf, Rr, sumC, dqdT, dqdC;               // reaction scratch
+  int red, total;
+  __host__ __device__ void make(int N_, int I_, int n_, bool mixed, int BS) {
+    N = N_; I = I_; n = n_;
+    lda = (n % 2 == 0) ? n + 1 : n;
+    int o = 0;
+    Yin = o; o += N; Hin = o; o += N;
+    x = o; o += n; xnw = o; o += n; xev = o; o += n; d = o; o += n; t = o; o += n;
+    M = o; o += n; G = o; o += n; rs = o; o += n; cs = o; o += n; rb = o; o += n; rr = o; o += n;
+    A64 = o; o += n * lda;
+    A32 = o; o += mixed ? (n * lda + 1) / 2 : 0;
+    piv = o; o += (n + 1) / 2;
+    persist = o;
+    C = o; o += N; hRT = o; o += N; sR = o; o += N; cpR = o; o += N; wdot = o; o += N;
+    gross = o; o += N; Erow = o; o += N; dwdT = o; o += N;
+    kf = o; o += I; kr = o; o += I; Rf = o; o += I; Rr = o; o += I;
+    sumC = o; o += I; dqdT = o; o += I; dqdC = o; o += 6 * I;
+    red = o; o += BS + 8;
+    total = o;
+  }
+};
+
+// ---------------------------------------------------------------- reductions
+
+template <int BS>
+__device__ inline double block_sum(double v, double *red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < BS / 64; w++) s += red[w];
+  return s;
+}
+
+// Max with NaN treated as +inf.
+template <int BS>
+__device__ inline double block_max(double v, double *red) {
+  if (v != v) v = __builtin_inf();
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = red[0];
+  for (int w = 1; w < BS / 64; w++) s = fmax(s, red[w]);
+  return s;
+}
+
+template <int BS>
+__device__ inline int block_or(int v, double *red) {
+  double s = block_max<BS>(v ? 1.0 : 0.0, red);
+  return s > 0.0;
+}
+
+// ------------------------------------------------------- reactor evaluation
+
+// Per-reactor context: pointers into the reactor's LDS (or workspace) area.
+struct Ctx {
+  MechDev m;
+  int N, n, energy;
+  double P, tau, Tin;
+  double *base;  // start of the reactor's area (doubles)
+  Layout L;
+  // scalars of the last residual evaluation
+  double T, S, rho, mdot;
+  __device__ double *p(int off) const { return base + off; }
+};
+
+// Set up a reactor: inlet composition and molar inlet enthalpies H_i(T_in).
+template <int BS>
+__device__ void load_inlet(Ctx &c, const double *Yin_soa, int64_t B, int64_t b) {
+  double *Yin = c.p(c.L.Yin), *Hin = c.p(c.L.Hin);
+  const double Tin = c.Tin;
+  for (int i = threadIdx.x; i < c.N; i += BS) {
+    Yin[i] = Yin_soa[(int64_t)i * B + b];
+    const double *a = c.m.nasa + 7 * i;
+    double hRT = a[0] + Tin * (a[1] / 2.0 + Tin * (a[2] / 3.0 + Tin * (a[3] / 4.0 + Tin * a[4] / 5.0)))
+                 + a[5] / Tin;
+    Hin[i] = kR * Tin * hRT;
+  }
+}
+
+// Steady residual F(x) (Eq. 2 and Eq. 3 times -rho V) with the rates of
+// Eqs. 4-9.  Leaves C, thermo, k_f, k_r, forward/reverse terms and wdot in
+// the context for the Jacobian.  Returns the scaled residual if asked for
+// (each equation's residual over the sum of the magnitudes of its terms).
+template <int BS>
+__device__ double residual(Ctx &c, const double *x, double *F, bool want_sres) {
+  const MechDev &m = c.m;
+  const int N = c.N, I = m.I, tid = threadIdx.x;
+  double *red = c.p(c.L.red);
+  double *C = c.p(c.L.C), *hRT = c.p(c.L.hRT), *sR = c.p(c.L.sR), *cpR = c.p(c.L.cpR);
+  double *wdot = c.p(c.L.wdot), *gross = c.p(c.L.gross);
+  double *kf = c.p(c.L.kf), *kr = c.p(c.L.kr), *Rf = c.p(c.L.Rf), *Rr = c.p(c.L.Rr);
+  const double *Yin = c.p(c.L.Yin), *Hin = c.p(c.L.Hin);
+
+  const double T = c.energy ? x[N] : c.Tin;
+  double s = 0.0;
+  for (int i = tid; i < N; i += BS) s += x[i] / m.W[i];
+  const double S = block_sum<BS>(s, red);
+  const double rho = c.P * 1.0e-6 / (kR * T * S);
+  const double mdot = rho * kV / c.tau;
+  c.T = T; c.S = S; c.rho = rho; c.mdot = mdot;
+  const double lnT = log(T), invT = 1.0 / T;
+  const double lnc = log(kPatm * 1.0e-6 / (kR * T));
+
+  // species: concentrations and NASA-7 thermo (the S, H of Eq. 9)
+  for (int i = tid; i < N; i += BS) {
+    C[i] = rho * x[i] / m.W[i];
+    const double *a = m.nasa + 7 * i;
+    cpR[i] = a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4])));
+    hRT[i] = a[0] + T * (a[1] / 2.0 + T * (a[2] / 3.0 + T * (a[3] / 4.0 + T * a[4] / 5.0))) + a[5] * invT;
+    sR[i] = a[0] * lnT + T * (a[1] + T * (a[2] / 2.0 + T * (a[3] / 3.0 + T * a[4] / 4.0))) + a[6];
+  }
+  __syncthreads();
+  // reactions: Eq. 6 (k_f), Eqs. 8-9 (K_c), Eq. 7 (k_r), Eq. 5 (q)
+  for (int k = tid; k < I; k += BS) {
+    double g = 0.0, fwd = 1.0, rev = 1.0;
+    for (int sl = 0; sl < 3; sl++) {
+      const int ir = m.r_idx[3 * k + sl];
+      if (ir >= 0) {
+        const int nu = m.r_nu[3 * k + sl];
+        g -= nu * (sR[ir] - hRT[ir]);
+        for (int e = 0; e < nu; e++) fwd *= C[ir];
+      }
+      const int ip = m.p_idx[3 * k + sl];
+      if (ip >= 0) {
+        const int nu = m.p_nu[3 * k + sl];
+        g += nu * (sR[ip] - hRT[ip]);
+        for (int e = 0; e < nu; e++) rev *= C[ip];
+      }
+    }
+    const double lnkf = m.lnA[k] + m.beta[k] * lnT - m.EoR[k] * invT;
+    const double lnKc = g + m.dnu[k] * lnc;
+    const double kfk = exp(lnkf), krk = exp(lnkf - lnKc);
+    kf[k] = kfk; kr[k] = krk;
+    fwd *= kfk; rev *= krk;
+    Rf[k] = fwd; Rr[k] = rev;
+  }
+  __syncthreads();
+  // species: Eq. 4 and the species residual
+  double inflow = 0.0, chem = 0.0, sr = 0.0;
+  for (int i = tid; i < N; i += BS) {
+    double w = 0.0, gr = 0.0;
+    for (int p = m.sp_ptr[i]; p < m.sp_ptr[i + 1]; p++) {
+      const int k = m.sp_rx[p];
+      w += m.sp_nu[p] * (Rf[k] - Rr[k]);
+      if (want_sres) gr += fabs((double)m.sp_nu[p]) * (fabs(Rf[k]) + fabs(Rr[k]));
+    }
+    wdot[i] = w;
+    gross[i] = gr;
+    const double Fi = mdot * (x[i] - Yin[i]) - kV * m.W[i] * w;
+    F[i] = Fi;
+    if (c.energy) {
+      const double H = kR * T * hRT[i];
+      inflow += Yin[i] * (H - Hin[i]) / m.W[i];
+      chem += H * w;
+    }
+    if (want_sres) {
+      const double den = mdot * (fabs(x[i]) + fabs(Yin[i])) + kV * m.W[i] * gr;
+      double r = (den > 0.0) ? fabs(Fi) / den : 0.0;
+      if (!(den >= 0.0) || Fi != Fi) r = __builtin_inf();
+      sr = fmax(sr, r);
+    }
+  }
+  double FT = 0.0;
+  if (c.energy) {
+    const double in_s = block_sum<BS>(inflow, red);
+    const double ch_s = block_sum<BS>(chem, red);
+    FT = mdot * in_s + kV * ch_s;
+    if (tid == 0) F[N] = FT;
+  }
+  double sres = 0.0;
+  if (want_sres) {
+    if (c.energy) {
+      double den = 0.0;
+      for (int i = tid; i < N; i += BS) {
+        const double H = kR * T * hRT[i];
+        den += mdot * fabs(Yin[i] * (H - Hin[i]) / m.W[i]) + kV * fabs(H) * gross[i];
+      }
+      den = block_sum<BS>(den, red);
+      if (tid == 0) {
+        double r = (den > 0.0) ? fabs(FT) / den : 0.0;
+        if (FT != FT) r = __builtin_inf();
+        sr = fmax(sr, r);
+      }
+    }
+    sres = block_max<BS>(sr, red);
+  }
+  __syncthreads();
+  return sres;
+}
+
+// Mass-matrix diagonal of the transient form: rho V (species), rho V cp_mix
+// (energy).  Uses the state of the last residual() call at the same x.
+template <int BS>
+__device__ void mass_diag(Ctx &c, const double *x, double *M) {
+  const int N = c.N, tid = threadIdx.x;
+  double *red = c.p(c.L.red);
+  const double *cpR = c.p(c.L.cpR);
+  double cp = 0.0;
+  if (c.energy)
+    for (int i = tid; i < N; i += BS) cp += x[i] * kR * cpR[i] / c.m.W[i];
+  const double cpmix = c.energy ? block_sum<BS>(cp, red) : 0.0;
+  for (int i = tid; i < N; i += BS) M[i] = c.rho * kV;
+  if (c.energy && tid == 0) M[N] = c.rho * kV * cpmix;
+  __syncthreads();
+}
+
+// Analytic Jacobian of residual() at the same x, into A (row-major, lda).
+// Chain rule through rho(Y,T), C(Y,T), k_f(T), K_c(T):
+//   dC_j/dY_m = rho delta_jm / W_j - C_j/(S W_m),  dC_j/dT = -C_j/T
+//   d ln k_f/dT = beta/T + E/(R T^2),  d ln K_c/dT = sum nu_i (H_i/RT)/T - dnu/T
+// D_im = sum_k nu_ik dq_k/dC_m is gathered row by row (row i owned by one
+// thread, so the accumulation order is fixed), then the rank-one density
+// terms are applied.
+template <int BS>
+__device__ void jacobian(Ctx &c, const double *x, double *A, int lda) {
+  const MechDev &m = c.m;
+  const int N = c.N, n = c.n, I = m.I, tid = threadIdx.x;
+  double *red = c.p(c.L.red);
+  const double *C = c.p(c.L.C), *hRT = c.p(c.L.hRT), *cpR = c.p(c.L.cpR), *wdot = c.p(c.L.wdot);
+  const double *kf = c.p(c.L.kf), *kr = c.p(c.L.kr), *Rf = c.p(c.L.Rf), *Rr = c.p(c.L.Rr);
+  double *sumC = c.p(c.L.sumC), *dqdT = c.p(c.L.dqdT), *dqdC = c.p(c.L.dqdC);
+  double *Erow = c.p(c.L.Erow), *dwdT = c.p(c.L.dwdT);
+  const double *Yin = c.p(c.L.Yin), *Hin = c.p(c.L.Hin);
+  const double T = c.T, S = c.S, rho = c.rho, mdot = c.mdot, invT = 1.0 / T;
+
+  for (int k = tid; k < I; k += BS) {
+    double sc = 0.0, sh = 0.0;
+    for (int sl = 0; sl < 3; sl++) {
+      const int ir = m.r_idx[3 * k + sl];
+      double dr = 0.0;
+      if (ir >= 0) {
+        dr = kf[k] * m.r_nu[3 * k + sl];
+        for (int e = 0; e < m.r_nu[3 * k + sl] - 1; e++) dr *= C[ir];
+        for (int s2 = 0; s2 < 3; s2++) {
+          const int j = m.r_idx[3 * k + s2];
+          if (s2 != sl && j >= 0)
+            for (int e = 0; e < m.r_nu[3 * k + s2]; e++) dr *= C[j];
+        }
+        sc += C[ir] * dr;
+        sh -= m.r_nu[3 * k + sl] * hRT[ir];
+      }
+      dqdC[6 * k + sl] = dr;
+      const int ip = m.p_idx[3 * k + sl];
+      double dp = 0.0;
+      if (ip >= 0) {
+        dp = kr[k] * m.p_nu[3 * k + sl];
+        for (int e = 0; e < m.p_nu[3 * k + sl] - 1; e++) dp *= C[ip];
+        for (int s2 = 0; s2 < 3; s2++) {
+          const int j = m.p_idx[3 * k + s2];
+          if (s2 != sl && j >= 0)
+            for (int e = 0; e < m.p_nu[3 * k + s2]; e++) dp *= C[j];
+        }
+        dp = -dp;
+        sc += C[ip] * dp;
+        sh += m.p_nu[3 * k + sl] * hRT[ip];
+      }
+      dqdC[6 * k + 3 + sl] = dp;
+    }
+    const double dlnkf = m.beta[k] * invT + m.EoR[k] * invT * invT;
+    const double dlnKc = sh * invT - m.dnu[k] * invT;
+    sumC[k] = sc;
+    dqdT[k] = Rf[k] * dlnkf - Rr[k] * (dlnkf - dlnKc) - sc * invT;
+  }
+  for (int e = tid; e < n * n; e += BS) A[(e / n) * lda + (e % n)] = 0.0;
+  __syncthreads();
+  // gather D (into the species rows of A), E_i = sum_j D_ij C_j, dwdot_i/dT
+  for (int i = tid; i < N; i += BS) {
+    double E = 0.0, dT = 0.0;
+    double *row = A + (int64_t)i * lda;
+    for (int p = m.sp_ptr[i]; p < m.sp_ptr[i + 1]; p++) {
+      const int k = m.sp_rx[p];
+      const double nu = m.sp_nu[p];
+      for (int sl = 0; sl < 3; sl++) {
+        const int ir = m.r_idx[3 * k + sl];
+        if (ir >= 0) row[ir] += nu * dqdC[6 * k + sl];
+        const int ip = m.p_idx[3 * k + sl];
+        if (ip >= 0) row[ip] += nu * dqdC[6 * k + 3 + sl];
+      }
+      E += nu * sumC[k];
+      dT += nu * dqdT[k];
+    }
+    Erow[i] = E;
+    dwdT[i] = dT;
+  }
+  __syncthreads();
+  if (c.energy) {
+    // energy row: dF_T/dY_m = -mdot Q_in/(S W_m) + V sum_i H_i dwdot_i/dY_m
+    double qin = 0.0, dqin = 0.0, tt = 0.0, hE = 0.0;
+    for (int i = tid; i < N; i += BS) {
+      const double H = kR * T * hRT[i];
+      qin += Yin[i] * (H - Hin[i]) / m.W[i];
+      dqin += Yin[i] * kR * cpR[i] / m.W[i];
+      tt += kV * (kR * cpR[i] * wdot[i] + H * dwdT[i]);
+      hE += H * Erow[i];
+    }
+    const double Qin = block_sum<BS>(qin, red);
+    const double dQin = block_sum<BS>(dqin, red);
+    const double TT = block_sum<BS>(tt, red);
+    const double HE = block_sum<BS>(hE, red);
+    for (int mm = tid; mm < N; mm += BS) {
+      double v = 0.0;
+      for (int i = 0; i < N; i++) v += kR * T * hRT[i] * A[(int64_t)i * lda + mm];
+      const double SW = S * m.W[mm];
+      A[(int64_t)N * lda + mm] = -mdot * Qin / SW + kV * (v * rho / m.W[mm] - HE / SW);
+    }
+    if (tid == 0) A[(int64_t)N * lda + N] = -mdot * invT * Qin + mdot * dQin + TT;
+    __syncthreads();
+  }
+  for (int i = tid; i < N; i += BS) {
+    double *row = A + (int64_t)i * lda;
+    const double yd = x[i] - Yin[i], Wi = m.W[i], Ei = Erow[i];
+    for (int mm = 0; mm < N; mm++) {
+      const double SW = S * m.W[mm];
+      double v = -mdot / SW * yd - kV * Wi * (row[mm] * rho / m.W[mm] - Ei / SW);
+      if (mm == i) v += mdot;
+      row[mm] = v;
+    }
+    if (c.energy) row[N] = -mdot * invT * yd - kV * Wi * dwdT[i];
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------- dense LU
+
+// In-place LU with partial pivoting of an n x n row-major matrix (leading
+// dimension lda) by one workgroup.  Pivot = first row index of the largest
+// |a_ik| at or below the diagonal; rows are swapped whole (LAPACK getrf
+// convention for piv).  Returns 0 or k+1 for a zero pivot column.
+template <int BS, typename T>
+__device__ int lu_factor(T *A, int n, int lda, int *piv, double *red) {
+  const int tid = threadIdx.x;
+  int *ipiv_s = reinterpret_cast<int *>(red + BS);
+  for (int k = 0; k < n; k++) {
+    if (tid < 64) {
+      double best = -1.0;
+      int bi = n;
+      for (int i = k + tid; i < n; i += 64) {
+        const double v = fabs((double)A[(int64_t)i * lda + k]);
+        if (v > best) { best = v; bi = i; }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (tid == 0) { ipiv_s[0] = bi; red[BS + 2] = best; }
+    }
+    __syncthreads();
+    const int p = ipiv_s[0];
+    const double amax = red[BS + 2];
+    if (tid == 0) piv[k] = p;
+    if (!(amax > 0.0)) {
+      __syncthreads();
+      return k + 1;
+    }
+    if (p != k) {
+      for (int j = tid; j < n; j += BS) {
+        const T t = A[(int64_t)k * lda + j];
+        A[(int64_t)k * lda + j] = A[(int64_t)p * lda + j];
+        A[(int64_t)p * lda + j] = t;
+      }
+      __syncthreads();
+    }
+    const T pivot = A[(int64_t)k * lda + k];
+    for (int i = k + 1 + tid; i < n; i += BS) A[(int64_t)i * lda + k] /= pivot;
+    __syncthreads();
+    const int m = n - k - 1;
+    for (int e = tid; e < m * m; e += BS) {
+      const int i = k + 1 + e / m, j = k + 1 + e % m;
+      A[(int64_t)i * lda + j] -= A[(int64_t)i * lda + k] * A[(int64_t)k * lda + j];
+    }
+    __syncthreads();
+  }
+  return 0;
+}
+
+// Solve (P L U) z = b in place (b in double; factors of type T).
+template <int BS, typename T>
+__device__ void lu_solve(const T *A, int n, int lda, const int *piv, double *b) {
+  const int tid = threadIdx.x;
+  if (tid == 0)
+    for (int k = 0; k < n; k++) {
+      const double t = b[k];
+      b[k] = b[piv[k]];
+      b[piv[k]] = t;
+    }
+  __syncthreads();
+  for (int k = 0; k < n - 1; k++) {
+    const double bk = b[k];
+    for (int i = k + 1 + tid; i < n; i += BS) b[i] -= (double)A[(int64_t)i * lda + k] * bk;
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; k--) {
+    const double bk = b[k] / (double)A[(int64_t)k * lda + k];
+    __syncthreads();
+    if (tid == 0) b[k] = bk;
+    for (int i = tid; i < k; i += BS) b[i] -= (double)A[(int64_t)i * lda + k] * bk;
+    __syncthreads();
+  }
+}
+
+}  // namespace psr

@@ -1,0 +1,625 @@
+// C ABI of the batched PSR solver: mechanism packing, kernels, schedulers.
+//
+// Kernels (one workgroup of kBS threads per reactor):
+//   k_residual     psr_residual: F(x) and the scaled residual (Eqs. 2-9)
+//   k_jacobian     psr_jacobian: analytic dF/dx
+//   k_lu_factor    psr_lu_factor_batch (FP64, or float factors)
+//   k_lu_solve     psr_lu_solve_batch
+//   k_round        plain scheduler: one controller round per launch, the
+//                  reactor's vectors and matrices kept in HBM between rounds
+//   k_persistent   persistent scheduler: workgroups pull reactors from a
+//                  device work queue and run each to completion in LDS
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include <cmath>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/psr.h"
+#include "psr_solver.hpp"
+
+using namespace psr;
+
+namespace {
+
+constexpr int kBS = 256;
+thread_local std::string g_err;
+
+psr_status fail(psr_status st, const std::string &msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIP_OK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(PSR_EDEVICE, std::string(#expr " failed: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+int lds_limit_bytes() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 65536;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return 65536;
+  return v;
+}
+
+}  // namespace
+
+struct psr_mech {
+  int E, N, I, nnz;
+  MechDev dev;
+  void *blob;  // one device allocation holding every table
+};
+
+// ------------------------------------------------------------------ kernels
+
+__device__ inline Ctx make_ctx(const MechDev &m, const Layout &L, int energy, double P, double tau,
+                               double Tin, double *base) {
+  Ctx c;
+  c.m = m;
+  c.N = m.N;
+  c.n = m.N + (energy ? 1 : 0);
+  c.energy = energy;
+  c.P = P;
+  c.tau = tau;
+  c.Tin = Tin;
+  c.base = base;
+  c.L = L;
+  return c;
+}
+
+__global__ void __launch_bounds__(kBS) k_residual(MechDev m, int energy, int64_t B, const double *P,
+                                                  const double *tau, const double *Tin,
+                                                  const double *Yin, const double *x, double *F,
+                                                  double *scaled) {
+  extern __shared__ double lds[];
+  const int64_t b = blockIdx.x;
+  Layout L;
+  L.make(m.N, m.I, m.N + (energy ? 1 : 0), false, kBS);
+  Ctx c = make_ctx(m, L, energy, P[b], tau[b], Tin[b], lds);
+  load_inlet<kBS>(c, Yin, B, b);
+  double *xl = c.p(L.x), *G = c.p(L.G);
+  for (int i = threadIdx.x; i < c.n; i += kBS) xl[i] = x[(int64_t)i * B + b];
+  __syncthreads();
+  const double sr = residual<kBS>(c, xl, G, scaled != nullptr);
+  for (int i = threadIdx.x; i < c.n; i += kBS) F[(int64_t)i * B + b] = G[i];
+  if (scaled && threadIdx.x == 0) scaled[b] = sr;
+}
+
+__global__ void __launch_bounds__(kBS) k_jacobian(MechDev m, int energy, int64_t B, const double *P,
+                                                  const double *tau, const double *Tin,
+                                                  const double *Yin, const double *x, double *J) {
+  extern __shared__ double lds[];
+  const int64_t b = blockIdx.x;
+  Layout L;
+  L.make(m.N, m.I, m.N + (energy ? 1 : 0), false, kBS);
+  Ctx c = make_ctx(m, L, energy, P[b], tau[b], Tin[b], lds);
+  load_inlet<kBS>(c, Yin, B, b);
+  double *xl = c.p(L.x), *G = c.p(L.G), *A = c.p(L.A64);
+  const int n = c.n;
+  for (int i = threadIdx.x; i < n; i += kBS) xl[i] = x[(int64_t)i * B + b];
+  __syncthreads();
+  residual<kBS>(c, xl, G, false);
+  jacobian<kBS>(c, xl, A, L.lda);
+  double *out = J + (int64_t)b * n * n;
+  for (int e = threadIdx.x; e < n * n; e += kBS) out[e] = A[(e / n) * L.lda + (e % n)];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBS) k_lu_factor(int n, double *A, int *piv, int *info) {
+  extern __shared__ double lds[];
+  const int64_t b = blockIdx.x;
+  const int lda = (n % 2 == 0) ? n + 1 : n;
+  T *M = reinterpret_cast<T *>(lds);
+  double *red = lds + (n * lda * sizeof(T) + 7) / 8;
+  int *pv = reinterpret_cast<int *>(red + kBS + 8);
+  double *g = A + b * (int64_t)n * n;
+  for (int e = threadIdx.x; e < n * n; e += kBS) M[(e / n) * lda + e % n] = (T)g[e];
+  __syncthreads();
+  const int r = lu_factor<kBS, T>(M, n, lda, pv, red);
+  for (int e = threadIdx.x; e < n * n; e += kBS) g[e] = (double)M[(e / n) * lda + e % n];
+  for (int k = threadIdx.x; k < n; k += kBS) piv[b * n + k] = (r == 0 || k < r) ? pv[k] : k;
+  if (threadIdx.x == 0) info[b] = r;
+}
+
+__global__ void __launch_bounds__(kBS) k_lu_solve(int n, const double *A, const int *piv, double *rhs) {
+  extern __shared__ double lds[];
+  const int64_t b = blockIdx.x;
+  const int lda = (n % 2 == 0) ? n + 1 : n;
+  double *M = lds, *z = lds + n * lda;
+  int *pv = reinterpret_cast<int *>(z + n);
+  const double *g = A + b * (int64_t)n * n;
+  for (int e = threadIdx.x; e < n * n; e += kBS) M[(e / n) * lda + e % n] = g[e];
+  for (int k = threadIdx.x; k < n; k += kBS) {
+    pv[k] = piv[b * n + k];
+    z[k] = rhs[b * n + k];
+  }
+  __syncthreads();
+  lu_solve<kBS, double>(M, n, lda, pv, z);
+  for (int k = threadIdx.x; k < n; k += kBS) rhs[b * n + k] = z[k];
+}
+
+// Inputs of one group as the kernels see them.
+struct GroupDev {
+  MechDev m;
+  int energy;
+  int64_t B;
+  const double *P, *tau, *Tin, *Yin;
+  double *x;       // [n][B]
+  int *status;     // [B]
+  int *nlin;       // [B] or null
+};
+
+__device__ inline void write_result(const GroupDev &g, const Ctx &c, const RState &s, int64_t b) {
+  const double *xl = c.p(c.L.x);
+  for (int i = threadIdx.x; i < c.n; i += kBS) g.x[(int64_t)i * g.B + b] = xl[i];
+  if (threadIdx.x == 0) {
+    g.status[b] = s.status;
+    if (g.nlin) g.nlin[b] = s.n_lin;
+  }
+}
+
+// Plain scheduler: one round per launch.  The persistent part of each
+// reactor's area lives in HBM (`area`, [B][persist]) between launches.
+template <bool MIXED, bool FIRST>
+__global__ void __launch_bounds__(kBS) k_round(GroupDev g, Opts o, RState *states, double *area,
+                                               int persist, int *active) {
+  extern __shared__ double lds[];
+  const int64_t b = blockIdx.x;
+  RState s = states[b];
+  if (!FIRST && s.phase == PH_DONE) return;
+  Layout L;
+  L.make(g.m.N, g.m.I, g.m.N + (g.energy ? 1 : 0), MIXED, kBS);
+  Ctx c = make_ctx(g.m, L, g.energy, g.P[b], g.tau[b], g.Tin[b], lds);
+  double *mine = area + b * (int64_t)persist;
+  if (FIRST) {
+    load_inlet<kBS>(c, g.Yin, g.B, b);
+    double *xl = c.p(L.x);
+    for (int i = threadIdx.x; i < c.n; i += kBS) xl[i] = g.x[(int64_t)i * g.B + b];
+    __syncthreads();
+    init_state<kBS>(c, o, s);
+  } else {
+    for (int e = threadIdx.x; e < persist; e += kBS) lds[e] = mine[e];
+    __syncthreads();
+    round_step<kBS, MIXED>(c, o, s);
+  }
+  if (s.phase == PH_DONE) {
+    write_result(g, c, s, b);
+  } else {
+    for (int e = threadIdx.x; e < persist; e += kBS) mine[e] = lds[e];
+    if (threadIdx.x == 0) atomicAdd(active, 1);
+  }
+  if (threadIdx.x == 0) states[b] = s;
+}
+
+// Persistent scheduler: grid sized to the resident capacity; each
+// workgroup takes the next reactor index from `queue` until none is left,
+// and runs it to completion with every array in LDS.
+template <bool MIXED>
+__global__ void __launch_bounds__(kBS) k_persistent(GroupDev g, Opts o, RState *states, int *queue) {
+  extern __shared__ double lds[];
+  Layout L;
+  L.make(g.m.N, g.m.I, g.m.N + (g.energy ? 1 : 0), MIXED, kBS);
+  int *next = reinterpret_cast<int *>(lds + L.red + kBS + 4);
+  for (;;) {
+    if (threadIdx.x == 0) *next = atomicAdd(queue, 1);
+    __syncthreads();
+    const int64_t b = *next;
+    __syncthreads();
+    if (b >= g.B) break;
+    Ctx c = make_ctx(g.m, L, g.energy, g.P[b], g.tau[b], g.Tin[b], lds);
+    load_inlet<kBS>(c, g.Yin, g.B, b);
+    double *xl = c.p(L.x);
+    for (int i = threadIdx.x; i < c.n; i += kBS) xl[i] = g.x[(int64_t)i * g.B + b];
+    __syncthreads();
+    RState s;
+    init_state<kBS>(c, o, s);
+    while (s.phase != PH_DONE) round_step<kBS, MIXED>(c, o, s);
+    write_result(g, c, s, b);
+    if (threadIdx.x == 0) states[b] = s;
+    __syncthreads();
+  }
+}
+
+__global__ void k_zero_int(int *p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// ------------------------------------------------------------ host: mechanism
+
+extern "C" const char *psr_last_error(void) { return g_err.c_str(); }
+
+extern "C" void psr_default_opts(psr_solve_opts *o) {
+  memset(o, 0, sizeof(*o));
+  o->precision = PSR_FP64;
+  o->scheduler = PSR_PLAIN;
+  o->rtol = 1e-10;
+  o->atol_Y = 1e-20;
+  o->atol_T = 1e-12;
+  o->ftol = 1e-10;
+  o->lambda_min = 1.0 / 16.0;
+  o->T_min = 300.0;
+  o->T_max = 3000.0;
+  o->ts_rtol = 0.1;
+  o->ts_atol_Y = 1e-6;
+  o->ts_atol_T = 1e-3;
+  o->ts_neg_tol = 1e-8;
+  o->h0 = 1e-6;
+  o->h_max = 1e6;
+  o->h_min = 1e-20;
+  o->nw_h_ratio = 1.0;
+  o->nw_max_it = 8;
+  o->nw_every = 10;
+  o->max_lin = 1000;
+  o->max_refine = 6;
+}
+
+extern "C" psr_status psr_create_mechanism(const psr_mech_desc *d, psr_mech_t *out) {
+  if (!d || !out) return fail(PSR_EINVAL, "null argument");
+  *out = nullptr;
+  const int E = d->n_elements, N = d->n_species, I = d->n_reactions;
+  if (E <= 0 || N <= 0 || I <= 0) return fail(PSR_EINVAL, "counts must be positive");
+  if (!d->elem_weight || !d->species_elems || !d->nasa7 || !d->reac_idx || !d->reac_nu ||
+      !d->prod_idx || !d->prod_nu || !d->A || !d->beta || !d->Ea)
+    return fail(PSR_EINVAL, "null table pointer");
+  if (!(d->t_low < d->t_high)) return fail(PSR_EINVAL, "t_low must be < t_high");
+  std::vector<double> W(N, 0.0);
+  for (int i = 0; i < N; i++) {
+    for (int e = 0; e < E; e++) {
+      if (d->species_elems[i * E + e] < 0)
+        return fail(PSR_EINVAL, "negative atom count, species " + std::to_string(i));
+      W[i] += d->species_elems[i * E + e] * d->elem_weight[e];
+    }
+    if (!(W[i] > 0.0)) return fail(PSR_EINVAL, "species " + std::to_string(i) + " has no weight");
+  }
+  std::vector<double> lnA(I), beta(I), EoR(I);
+  std::vector<int> dnu(I), ridx(3 * I), rnu(3 * I), pidx(3 * I), pnu(3 * I);
+  std::vector<std::vector<std::pair<int, int>>> bysp(N);
+  for (int k = 0; k < I; k++) {
+    if (!(d->A[k] > 0.0) || !std::isfinite(d->A[k]) || !std::isfinite(d->beta[k]) ||
+        !std::isfinite(d->Ea[k]))
+      return fail(PSR_EINVAL, "reaction " + std::to_string(k) + ": bad Arrhenius parameters");
+    lnA[k] = log(d->A[k]);
+    beta[k] = d->beta[k];
+    EoR[k] = d->Ea[k] / kR;
+    std::vector<long long> bal(E, 0);
+    std::vector<int> net(N, 0);
+    int nr = 0, np = 0, sum = 0;
+    for (int s = 0; s < 3; s++) {
+      const int ir = d->reac_idx[3 * k + s], ip = d->prod_idx[3 * k + s];
+      ridx[3 * k + s] = ir;
+      rnu[3 * k + s] = ir >= 0 ? d->reac_nu[3 * k + s] : 0;
+      pidx[3 * k + s] = ip;
+      pnu[3 * k + s] = ip >= 0 ? d->prod_nu[3 * k + s] : 0;
+      for (int side = 0; side < 2; side++) {
+        const int i = side ? ip : ir;
+        const int nu = side ? d->prod_nu[3 * k + s] : d->reac_nu[3 * k + s];
+        if (i < -1 || i >= N)
+          return fail(PSR_EINVAL, "reaction " + std::to_string(k) + ": species index out of range");
+        if (i < 0) continue;
+        if (nu < 1 || nu > 8)
+          return fail(PSR_EINVAL, "reaction " + std::to_string(k) + ": coefficient out of range");
+        const int sg = side ? 1 : -1;
+        if ((side && net[i] < 0) || (!side && net[i] > 0))
+          return fail(PSR_EINVAL, "reaction " + std::to_string(k) + ": species on both sides");
+        if (net[i] != 0)
+          return fail(PSR_EINVAL, "reaction " + std::to_string(k) + ": repeated species slot");
+        net[i] = sg * nu;
+        sum += sg * nu;
+        (side ? np : nr)++;
+        for (int e = 0; e < E; e++) bal[e] += (long long)sg * nu * d->species_elems[i * E + e];
+      }
+    }
+    if (nr == 0 || np == 0)
+      return fail(PSR_EINVAL, "reaction " + std::to_string(k) + ": empty side");
+    for (int e = 0; e < E; e++)
+      if (bal[e] != 0)
+        return fail(PSR_EINVAL, "reaction " + std::to_string(k) + ": not element balanced");
+    dnu[k] = sum;
+    for (int i = 0; i < N; i++)
+      if (net[i] != 0) bysp[i].push_back({k, net[i]});
+  }
+  std::vector<int> ptr(N + 1, 0), rx, nu;
+  for (int i = 0; i < N; i++) {
+    ptr[i + 1] = ptr[i] + (int)bysp[i].size();
+    for (auto &pr : bysp[i]) { rx.push_back(pr.first); nu.push_back(pr.second); }
+  }
+  const int nnz = ptr[N];
+  // one blob: doubles first, then ints
+  const size_t nd = (size_t)N + 7 * N + 3 * I;
+  const size_t ni = (size_t)I + 12 * I + (N + 1) + 2 * std::max(nnz, 1);
+  std::vector<char> host(nd * 8 + ni * 4);
+  double *hd = reinterpret_cast<double *>(host.data());
+  int *hi = reinterpret_cast<int *>(host.data() + nd * 8);
+  size_t od = 0, oi = 0;
+  auto putd = [&](const double *src, size_t cnt) { memcpy(hd + od, src, cnt * 8); od += cnt; return od - cnt; };
+  auto puti = [&](const int *src, size_t cnt) { if (cnt) memcpy(hi + oi, src, cnt * 4); oi += cnt; return oi - cnt; };
+  const size_t oW = putd(W.data(), N), oNasa = putd(d->nasa7, 7 * (size_t)N);
+  const size_t olnA = putd(lnA.data(), I), obeta = putd(beta.data(), I), oEoR = putd(EoR.data(), I);
+  const size_t odnu = puti(dnu.data(), I), orI = puti(ridx.data(), 3 * I), orN = puti(rnu.data(), 3 * I);
+  const size_t opI = puti(pidx.data(), 3 * I), opN = puti(pnu.data(), 3 * I);
+  const size_t optr = puti(ptr.data(), N + 1), orx = puti(rx.data(), nnz), onu = puti(nu.data(), nnz);
+  for (int i = 0; i < N * 7; i++)
+    if (!std::isfinite(d->nasa7[i])) return fail(PSR_EINVAL, "non-finite NASA-7 coefficient");
+  void *blob = nullptr;
+  HIP_OK(hipMalloc(&blob, host.size()));
+  if (hipMemcpy(blob, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    hipFree(blob);
+    return fail(PSR_EDEVICE, "hipMemcpy of mechanism tables failed");
+  }
+  psr_mech *m = new psr_mech();
+  m->E = E; m->N = N; m->I = I; m->nnz = nnz; m->blob = blob;
+  const double *bd = reinterpret_cast<const double *>(blob);
+  const int *bi = reinterpret_cast<const int *>(reinterpret_cast<const char *>(blob) + nd * 8);
+  m->dev.N = N; m->dev.I = I; m->dev.nnz = nnz;
+  m->dev.W = bd + oW; m->dev.nasa = bd + oNasa;
+  m->dev.lnA = bd + olnA; m->dev.beta = bd + obeta; m->dev.EoR = bd + oEoR;
+  m->dev.dnu = bi + odnu; m->dev.r_idx = bi + orI; m->dev.r_nu = bi + orN;
+  m->dev.p_idx = bi + opI; m->dev.p_nu = bi + opN;
+  m->dev.sp_ptr = bi + optr; m->dev.sp_rx = bi + orx; m->dev.sp_nu = bi + onu;
+  *out = m;
+  return PSR_OK;
+}
+
+extern "C" psr_status psr_destroy_mechanism(psr_mech_t m) {
+  if (!m) return PSR_OK;
+  hipError_t e = hipFree(m->blob);
+  delete m;
+  if (e != hipSuccess) return fail(PSR_EDEVICE, "hipFree failed");
+  return PSR_OK;
+}
+
+extern "C" int32_t psr_num_unknowns(psr_mech_t m, int32_t energy) {
+  return m ? m->N + (energy ? 1 : 0) : -1;
+}
+
+// ------------------------------------------------------------ host: kernels
+
+static psr_status check_cond(psr_mech_t m, const psr_conditions *c) {
+  if (!m || !c) return fail(PSR_EINVAL, "null argument");
+  if (c->n_reactors <= 0) return fail(PSR_EINVAL, "n_reactors must be positive");
+  if (c->n_reactors > 0x7fffffffLL) return fail(PSR_EUNSUPPORTED, "n_reactors above 2^31-1");
+  if (!c->P || !c->tau || !c->T_in || !c->Y_in) return fail(PSR_EINVAL, "null condition pointer");
+  return PSR_OK;
+}
+
+static size_t layout_bytes(psr_mech_t m, int energy, bool mixed) {
+  Layout L;
+  L.make(m->N, m->I, m->N + (energy ? 1 : 0), mixed, kBS);
+  return (size_t)L.total * 8;
+}
+
+extern "C" psr_status psr_residual(psr_mech_t m, const psr_conditions *c, const double *x, double *F,
+                                   double *scaled, void *stream) {
+  psr_status st = check_cond(m, c);
+  if (st != PSR_OK) return st;
+  if (!x || !F) return fail(PSR_EINVAL, "null x or F");
+  const size_t lds = layout_bytes(m, c->energy, false);
+  if (lds > (size_t)lds_limit_bytes()) return fail(PSR_EUNSUPPORTED, "mechanism too large for LDS");
+  hipLaunchKernelGGL(k_residual, dim3((unsigned)c->n_reactors), dim3(kBS), lds, (hipStream_t)stream,
+                     m->dev, c->energy ? 1 : 0, c->n_reactors, c->P, c->tau, c->T_in, c->Y_in, x, F,
+                     scaled);
+  HIP_OK(hipGetLastError());
+  return PSR_OK;
+}
+
+extern "C" psr_status psr_jacobian(psr_mech_t m, const psr_conditions *c, const double *x, double *J,
+                                   void *stream) {
+  psr_status st = check_cond(m, c);
+  if (st != PSR_OK) return st;
+  if (!x || !J) return fail(PSR_EINVAL, "null x or J");
+  const size_t lds = layout_bytes(m, c->energy, false);
+  if (lds > (size_t)lds_limit_bytes()) return fail(PSR_EUNSUPPORTED, "mechanism too large for LDS");
+  hipLaunchKernelGGL(k_jacobian, dim3((unsigned)c->n_reactors), dim3(kBS), lds, (hipStream_t)stream,
+                     m->dev, c->energy ? 1 : 0, c->n_reactors, c->P, c->tau, c->T_in, c->Y_in, x, J);
+  HIP_OK(hipGetLastError());
+  return PSR_OK;
+}
+
+extern "C" psr_status psr_lu_factor_batch(int32_t n, int64_t batch, int32_t precision, double *A,
+                                          int32_t *piv, int32_t *info, void *stream) {
+  if (n <= 0 || batch <= 0 || !A || !piv || !info) return fail(PSR_EINVAL, "bad LU arguments");
+  if (batch > 0x7fffffffLL) return fail(PSR_EUNSUPPORTED, "batch above 2^31-1");
+  const int lda = (n % 2 == 0) ? n + 1 : n;
+  const bool f32 = precision == PSR_MIXED;
+  const size_t lds = ((size_t)n * lda * (f32 ? 4 : 8) + 7) / 8 * 8 + (kBS + 8) * 8 + (size_t)n * 4 + 8;
+  if (lds > (size_t)lds_limit_bytes()) return fail(PSR_EUNSUPPORTED, "matrix too large for LDS");
+  if (f32)
+    hipLaunchKernelGGL(k_lu_factor<float>, dim3((unsigned)batch), dim3(kBS), lds, (hipStream_t)stream,
+                       n, A, piv, info);
+  else
+    hipLaunchKernelGGL(k_lu_factor<double>, dim3((unsigned)batch), dim3(kBS), lds, (hipStream_t)stream,
+                       n, A, piv, info);
+  HIP_OK(hipGetLastError());
+  return PSR_OK;
+}
+
+extern "C" psr_status psr_lu_solve_batch(int32_t n, int64_t batch, const double *LU, const int32_t *piv,
+                                         double *b, void *stream) {
+  if (n <= 0 || batch <= 0 || !LU || !piv || !b) return fail(PSR_EINVAL, "bad LU arguments");
+  if (batch > 0x7fffffffLL) return fail(PSR_EUNSUPPORTED, "batch above 2^31-1");
+  const int lda = (n % 2 == 0) ? n + 1 : n;
+  const size_t lds = (size_t)n * lda * 8 + (size_t)n * 8 + (size_t)n * 4 + 8;
+  if (lds > (size_t)lds_limit_bytes()) return fail(PSR_EUNSUPPORTED, "matrix too large for LDS");
+  hipLaunchKernelGGL(k_lu_solve, dim3((unsigned)batch), dim3(kBS), lds, (hipStream_t)stream, n, LU, piv,
+                     b);
+  HIP_OK(hipGetLastError());
+  return PSR_OK;
+}
+
+// ------------------------------------------------------------ host: solve
+
+static Opts to_dev_opts(const psr_solve_opts *o) {
+  Opts d;
+  d.precision = o->precision; d.scheduler = o->scheduler;
+  d.rtol = o->rtol; d.atol_Y = o->atol_Y; d.atol_T = o->atol_T; d.ftol = o->ftol;
+  d.lambda_min = o->lambda_min; d.T_min = o->T_min; d.T_max = o->T_max;
+  d.ts_rtol = o->ts_rtol; d.ts_atol_Y = o->ts_atol_Y; d.ts_atol_T = o->ts_atol_T;
+  d.ts_neg_tol = o->ts_neg_tol; d.h0 = o->h0; d.h_max = o->h_max; d.h_min = o->h_min;
+  d.nw_h_ratio = o->nw_h_ratio; d.nw_max_it = o->nw_max_it; d.nw_every = o->nw_every;
+  d.max_lin = o->max_lin; d.max_refine = o->max_refine;
+  return d;
+}
+
+static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+// Workspace of one group: states [B], plain-scheduler areas [B][persist],
+// counters.
+static size_t group_ws(const psr_group &g, const psr_solve_opts *o) {
+  Layout L;
+  const bool mixed = o->precision == PSR_MIXED;
+  L.make(g.mech->N, g.mech->I, g.mech->N + (g.cond.energy ? 1 : 0), mixed, kBS);
+  size_t bytes = align256(sizeof(RState) * (size_t)g.cond.n_reactors) + 256;
+  if (o->scheduler == PSR_PLAIN) bytes += align256((size_t)L.persist * 8 * g.cond.n_reactors);
+  return bytes;
+}
+
+extern "C" size_t psr_workspace_bytes(const psr_group *groups, int32_t n_groups,
+                                      const psr_solve_opts *opts) {
+  if (!groups || n_groups <= 0 || !opts) return 0;
+  size_t mx = 0;
+  for (int gi = 0; gi < n_groups; gi++) {
+    if (!groups[gi].mech || groups[gi].cond.n_reactors <= 0) return 0;
+    mx = std::max(mx, group_ws(groups[gi], opts));
+  }
+  return mx;
+}
+
+static psr_status check_opts(const psr_solve_opts *o) {
+  if (!o) return fail(PSR_EINVAL, "null opts");
+  if (o->precision != PSR_FP64 && o->precision != PSR_MIXED) return fail(PSR_EINVAL, "bad precision");
+  if (o->scheduler != PSR_PLAIN && o->scheduler != PSR_PERSISTENT) return fail(PSR_EINVAL, "bad scheduler");
+  if (!(o->rtol > 0) || !(o->atol_Y >= 0) || !(o->atol_T >= 0) || !(o->ftol > 0) ||
+      !(o->lambda_min > 0 && o->lambda_min <= 1) || !(o->T_min < o->T_max) || !(o->ts_rtol > 0) ||
+      !(o->h0 > 0) || !(o->h_min > 0) || !(o->h_max > 0) || o->nw_max_it < 1 || o->nw_every < 1 ||
+      o->max_lin < 1 || o->max_refine < 0)
+    return fail(PSR_EINVAL, "option out of range");
+  return PSR_OK;
+}
+
+static psr_status solve_group(const psr_group &g, const psr_solve_opts *o, void *ws, hipStream_t stream,
+                              psr_solve_stats *acc) {
+  const bool mixed = o->precision == PSR_MIXED;
+  const int64_t B = g.cond.n_reactors;
+  Layout L;
+  L.make(g.mech->N, g.mech->I, g.mech->N + (g.cond.energy ? 1 : 0), mixed, kBS);
+  const size_t lds = (size_t)L.total * 8;
+  if (lds > (size_t)lds_limit_bytes())
+    return fail(PSR_EUNSUPPORTED, "reactor working set (" + std::to_string(lds) +
+                                      " B) exceeds the LDS of one workgroup");
+  GroupDev gd;
+  gd.m = g.mech->dev; gd.energy = g.cond.energy ? 1 : 0; gd.B = B;
+  gd.P = g.cond.P; gd.tau = g.cond.tau; gd.Tin = g.cond.T_in; gd.Yin = g.cond.Y_in;
+  gd.x = g.x_inout; gd.status = g.status; gd.nlin = g.n_lin;
+  const Opts od = to_dev_opts(o);
+  char *p = reinterpret_cast<char *>(ws);
+  RState *states = reinterpret_cast<RState *>(p);
+  p += align256(sizeof(RState) * (size_t)B);
+  int *counters = reinterpret_cast<int *>(p);
+  p += 256;
+  double *area = reinterpret_cast<double *>(p);
+
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  HIP_OK(hipEventRecord(e0, stream));
+  int rounds = 0;
+  if (o->scheduler == PSR_PERSISTENT) {
+    int dev = 0, ncu = 0, per_cu = 0;
+    HIP_OK(hipGetDevice(&dev));
+    HIP_OK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    if (mixed)
+      HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<true>, kBS, lds));
+    else
+      HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<false>, kBS, lds));
+    if (per_cu < 1) per_cu = 1;
+    const int64_t grid = std::min<int64_t>(B, (int64_t)ncu * per_cu);
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, counters, 64);
+    if (mixed)
+      hipLaunchKernelGGL(k_persistent<true>, dim3((unsigned)grid), dim3(kBS), lds, stream, gd, od, states,
+                         counters);
+    else
+      hipLaunchKernelGGL(k_persistent<false>, dim3((unsigned)grid), dim3(kBS), lds, stream, gd, od, states,
+                         counters);
+    HIP_OK(hipGetLastError());
+  } else {
+    const int check_every = 4;
+    if (mixed)
+      hipLaunchKernelGGL((k_round<true, true>), dim3((unsigned)B), dim3(kBS), lds, stream, gd, od, states,
+                         area, L.persist, counters);
+    else
+      hipLaunchKernelGGL((k_round<false, true>), dim3((unsigned)B), dim3(kBS), lds, stream, gd, od, states,
+                         area, L.persist, counters);
+    HIP_OK(hipGetLastError());
+    int active = 1;
+    const int max_rounds = o->max_lin * 2 + 8;
+    while (active > 0 && rounds < max_rounds) {
+      hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, counters, 1);
+      for (int r = 0; r < check_every; r++) {
+        if (mixed)
+          hipLaunchKernelGGL((k_round<true, false>), dim3((unsigned)B), dim3(kBS), lds, stream, gd, od,
+                             states, area, L.persist, counters);
+        else
+          hipLaunchKernelGGL((k_round<false, false>), dim3((unsigned)B), dim3(kBS), lds, stream, gd, od,
+                             states, area, L.persist, counters);
+        rounds++;
+      }
+      HIP_OK(hipGetLastError());
+      HIP_OK(hipMemcpyAsync(&active, counters, sizeof(int), hipMemcpyDeviceToHost, stream));
+      HIP_OK(hipStreamSynchronize(stream));
+    }
+    if (active > 0) return fail(PSR_EDEVICE, "plain scheduler did not retire every reactor");
+  }
+  HIP_OK(hipEventRecord(e1, stream));
+  HIP_OK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (acc) {
+    std::vector<RState> hs(B);
+    HIP_OK(hipMemcpy(hs.data(), states, sizeof(RState) * B, hipMemcpyDeviceToHost));
+    acc->reactors += B;
+    for (const RState &s : hs) {
+      acc->converged += s.status == RS_CONVERGED;
+      acc->lin_total += s.n_lin;
+      acc->lin_max = std::max<int64_t>(acc->lin_max, s.n_lin);
+      acc->jac_total += s.n_jac;
+      acc->fp64_fallbacks += s.n_fb64;
+    }
+    acc->rounds += rounds;
+    acc->kernel_ms += ms;
+  }
+  return PSR_OK;
+}
+
+extern "C" psr_status psr_solve_batch(const psr_group *groups, int32_t n_groups, const psr_solve_opts *opts,
+                                      void *workspace, size_t workspace_bytes, psr_solve_stats *stats,
+                                      void *stream) {
+  psr_status st = check_opts(opts);
+  if (st != PSR_OK) return st;
+  if (!groups || n_groups <= 0) return fail(PSR_EINVAL, "no groups");
+  for (int gi = 0; gi < n_groups; gi++) {
+    st = check_cond(groups[gi].mech, &groups[gi].cond);
+    if (st != PSR_OK) return st;
+    if (!groups[gi].x_inout || !groups[gi].status) return fail(PSR_EINVAL, "null x_inout or status");
+  }
+  const size_t need = psr_workspace_bytes(groups, n_groups, opts);
+  if (!workspace || workspace_bytes < need)
+    return fail(PSR_ENOMEM, "workspace smaller than psr_workspace_bytes() = " + std::to_string(need));
+  if (stats) memset(stats, 0, sizeof(*stats));
+  for (int gi = 0; gi < n_groups; gi++) {
+    st = solve_group(groups[gi], opts, workspace, (hipStream_t)stream, stats);
+    if (st != PSR_OK) return st;
+  }
+  return PSR_OK;
+}

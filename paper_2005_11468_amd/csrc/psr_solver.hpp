@@ -1,0 +1,384 @@
+// The per-reactor controller of the hybrid method (Section 3) as a round
+// machine, plus the linear-algebra step of each round in FP64 or in mixed
+// precision (FP32 factors + FP64 iterative refinement).
+//
+// A round is: one residual evaluation at the current evaluation point, a
+// Jacobian + factorisation when the phase starts a new linearisation, one
+// (possibly refined) solve, and the controller's decision.  Every thread of
+// the workgroup runs the same scalar decisions on the same block-reduced
+// values, so the controller state stays replicated without extra traffic.
+//
+// Phases:
+//   NW_BASE   Newton iterate: F, J, LU, d = -J^-1 F, convergence test,
+//             damping start.
+//   NW_TRIAL  trial point x + lam d of the natural criterion, solved with
+//             the same factors.
+//   TS1, TS2  the two stages of one ROS2 step of M dx/dt = -F(x).
+#pragma once
+
+#include "psr_device.hpp"
+
+namespace psr {
+
+template <int BS>
+__device__ inline void vcopy(double *dst, const double *src, int n) {
+  for (int i = threadIdx.x; i < n; i += BS) dst[i] = src[i];
+  __syncthreads();
+}
+
+// Weighted max norm of a Newton step: max_k |v_k| / (atol_k + rtol |x_k|).
+template <int BS>
+__device__ inline double newton_norm(const Ctx &c, const Opts &o, const double *x, const double *v,
+                                     double *red) {
+  double r = 0.0;
+  for (int k = threadIdx.x; k < c.n; k += BS) {
+    const double w = (k < c.N ? o.atol_Y : o.atol_T) + o.rtol * fabs(x[k]);
+    double t = fabs(v[k]) / w;
+    if (t != t) t = __builtin_inf();
+    r = fmax(r, t);
+  }
+  return block_max<BS>(r, red);
+}
+
+// out = x + lam d, Y projected onto Y >= 0, T onto [T_min, T_max].
+template <int BS>
+__device__ inline void step_clamped(const Ctx &c, const Opts &o, const double *x, double lam,
+                                    const double *d, double *out) {
+  for (int i = threadIdx.x; i < c.n; i += BS) {
+    double v = x[i] + lam * d[i];
+    if (i < c.N) v = v > 0.0 ? v : 0.0;
+    else v = v < o.T_min ? o.T_min : (v > o.T_max ? o.T_max : v);
+    out[i] = v;
+  }
+  __syncthreads();
+}
+
+template <int BS>
+__device__ inline int all_finite(const double *v, int n, double *red) {
+  int bad = 0;
+  for (int i = threadIdx.x; i < n; i += BS) bad |= !isfinite(v[i]);
+  return !block_or<BS>(bad, red);
+}
+
+template <int BS>
+__device__ inline int matrix_finite(const double *A, int n, int lda, double *red) {
+  int bad = 0;
+  for (int e = threadIdx.x; e < n * n; e += BS) bad |= !isfinite(A[(e / n) * lda + (e % n)]);
+  return !block_or<BS>(bad, red);
+}
+
+// ---------------------------------------------------------- linear algebra
+
+// Mixed precision: scale rows, then columns, of A64 by powers of two (exact)
+// so every row and column has max magnitude in [1/2, 1), round to float into
+// A32 and factor there.  Returns the float LU's status.
+template <int BS>
+__device__ int factor_mixed(const Ctx &c, const double *A64, float *A32, int *piv, double *rs,
+                            double *cs, double *red) {
+  const int n = c.n, lda = c.L.lda;
+  for (int i = threadIdx.x; i < n; i += BS) {
+    double mx = 0.0;
+    for (int j = 0; j < n; j++) mx = fmax(mx, fabs(A64[(int64_t)i * lda + j]));
+    int e = 0;
+    if (mx > 0.0 && isfinite(mx)) frexp(mx, &e);
+    rs[i] = ldexp(1.0, -e);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < n; j += BS) {
+    double mx = 0.0;
+    for (int i = 0; i < n; i++) mx = fmax(mx, fabs(A64[(int64_t)i * lda + j] * rs[i]));
+    int e = 0;
+    if (mx > 0.0 && isfinite(mx)) frexp(mx, &e);
+    cs[j] = ldexp(1.0, -e);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * n; e += BS) {
+    const int i = e / n, j = e % n;
+    A32[(int64_t)i * lda + j] = (float)(A64[(int64_t)i * lda + j] * rs[i] * cs[j]);
+  }
+  __syncthreads();
+  return lu_factor<BS, float>(A32, n, lda, piv, red);
+}
+
+// z = A^-1 b with the float factors of the equilibrated matrix.
+template <int BS>
+__device__ inline void solve_scaled32(const Ctx &c, const float *A32, const int *piv, const double *rs,
+                                      const double *cs, const double *b, double *z) {
+  const int n = c.n;
+  for (int i = threadIdx.x; i < n; i += BS) z[i] = rs[i] * b[i];
+  __syncthreads();
+  lu_solve<BS, float>(A32, n, c.L.lda, piv, z);
+  for (int i = threadIdx.x; i < n; i += BS) z[i] *= cs[i];
+  __syncthreads();
+}
+
+// Solve A z = b for the current round's matrix.  FP64: z = LU64 \ b.
+// Mixed: float solve + FP64 iterative refinement against the unfactored
+// FP64 matrix (r = b - A z in FP64); refinement stops when the correction
+// is below 1e-10 of |z| in max norm; if the correction shrinks by less
+// than half, or max_refine sweeps do not reach that, the matrix is
+// refactored in FP64 for the rest of this linearisation.
+template <int BS, bool MIXED>
+__device__ void solve_round(const Ctx &c, const Opts &o, RState &s, const double *b, double *z) {
+  const int n = c.n, lda = c.L.lda;
+  double *red = c.p(c.L.red);
+  double *A64 = c.p(c.L.A64);
+  int *piv = reinterpret_cast<int *>(c.p(c.L.piv));
+  if (!MIXED || s.fb64) {
+    vcopy<BS>(z, b, n);
+    lu_solve<BS, double>(A64, n, lda, piv, z);
+    return;
+  }
+  const float *A32 = reinterpret_cast<const float *>(c.p(c.L.A32));
+  const double *rs = c.p(c.L.rs), *cs = c.p(c.L.cs);
+  double *r = c.p(c.L.rr), *bb = c.p(c.L.rb);
+  vcopy<BS>(bb, b, n);
+  solve_scaled32<BS>(c, A32, piv, rs, cs, bb, z);
+  double prev = __builtin_inf();
+  bool ok = false;
+  for (int it = 0; it < o.max_refine; it++) {
+    for (int i = threadIdx.x; i < n; i += BS) {
+      double acc = bb[i];
+      const double *row = A64 + (int64_t)i * lda;
+      for (int j = 0; j < n; j++) acc -= row[j] * z[j];
+      r[i] = acc;
+    }
+    __syncthreads();
+    solve_scaled32<BS>(c, A32, piv, rs, cs, r, r);
+    double dn = 0.0, zn = 0.0;
+    for (int i = threadIdx.x; i < n; i += BS) {
+      z[i] += r[i];
+      dn = fmax(dn, fabs(r[i]));
+      zn = fmax(zn, fabs(z[i]));
+    }
+    dn = block_max<BS>(dn, red);
+    zn = block_max<BS>(zn, red);
+    if (dn <= 1e-10 * zn) { ok = true; break; }
+    if (!(dn <= 0.5 * prev)) break;
+    prev = dn;
+  }
+  if (ok) return;
+  // FP64 fallback for this matrix
+  s.fb64 = 1;
+  s.n_fb64++;
+  const int info = lu_factor<BS, double>(A64, n, lda, piv, red);
+  s.sing = info != 0;
+  vcopy<BS>(z, bb, n);
+  if (!s.sing) lu_solve<BS, double>(A64, n, lda, piv, z);
+}
+
+// ---------------------------------------------------------------- rounds
+
+template <int BS>
+__device__ inline void finish(RState &s, int status) {
+  s.status = status;
+  s.phase = PH_DONE;
+}
+
+// Start one ROS2 step from x (budget: two linear solves).
+template <int BS>
+__device__ inline void start_ts(const Ctx &c, const Opts &o, RState &s) {
+  if (s.n_lin + 2 > o.max_lin) { finish<BS>(s, RS_MAXITER); return; }
+  s.phase = PH_TS1;
+  vcopy<BS>(c.p(c.L.xev), c.p(c.L.x), c.n);
+}
+
+// Start a steady Newton attempt from x.
+template <int BS>
+__device__ inline void start_attempt(const Ctx &c, const Opts &o, RState &s) {
+  s.n_att++;
+  s.nw_it = 0;
+  vcopy<BS>(c.p(c.L.xnw), c.p(c.L.x), c.n);
+  if (s.n_lin >= o.max_lin) { finish<BS>(s, RS_MAXITER); return; }
+  s.phase = PH_NW_BASE;
+  vcopy<BS>(c.p(c.L.xev), c.p(c.L.xnw), c.n);
+}
+
+// Next damped trial point, or the attempt has failed.
+template <int BS>
+__device__ inline void try_trial(const Ctx &c, const Opts &o, RState &s) {
+  if (s.lam >= o.lambda_min) {
+    if (s.n_lin >= o.max_lin) { finish<BS>(s, RS_MAXITER); return; }
+    step_clamped<BS>(c, o, c.p(c.L.xnw), s.lam, c.p(c.L.d), c.p(c.L.xev));
+    s.phase = PH_NW_TRIAL;
+  } else {
+    start_ts<BS>(c, o, s);
+  }
+}
+
+template <int BS>
+__device__ inline void reject_ts(const Ctx &c, const Opts &o, RState &s, bool bad, double err) {
+  double fac = bad ? 0.25 : 0.9 / sqrt(err);
+  s.h *= (fac < 0.2 ? 0.2 : fac);
+  if (s.h < o.h_min) finish<BS>(s, RS_TS_FAILED);
+  else start_ts<BS>(c, o, s);
+}
+
+// One round of the controller.
+template <int BS, bool MIXED>
+__device__ void round_step(Ctx &c, const Opts &o, RState &s) {
+  const Layout &L = c.L;
+  const int n = c.n, N = c.N, lda = L.lda;
+  double *red = c.p(L.red);
+  double *x = c.p(L.x), *xnw = c.p(L.xnw), *xev = c.p(L.xev), *d = c.p(L.d), *t = c.p(L.t);
+  double *M = c.p(L.M), *G = c.p(L.G), *A64 = c.p(L.A64);
+  int *piv = reinterpret_cast<int *>(c.p(L.piv));
+  const int ph = s.phase;
+  const bool lin = (ph == PH_NW_BASE || ph == PH_TS1);
+
+  const double sres = residual<BS>(c, xev, G, ph == PH_NW_BASE);
+  if (lin) {
+    jacobian<BS>(c, xev, A64, lda);
+    if (ph == PH_TS1) {
+      mass_diag<BS>(c, xev, M);
+      for (int i = threadIdx.x; i < n; i += BS) A64[(int64_t)i * lda + i] += M[i] / (kGamma * s.h);
+      __syncthreads();
+    }
+    s.n_jac++;
+    s.fb64 = 0;
+    s.fin = all_finite<BS>(G, n, red) && matrix_finite<BS>(A64, n, lda, red);
+    s.sing = 0;
+    if (s.fin) {
+      if (MIXED) {
+        const int info = factor_mixed<BS>(c, A64, reinterpret_cast<float *>(c.p(L.A32)), piv,
+                                          c.p(L.rs), c.p(L.cs), red);
+        if (info != 0) {
+          s.fb64 = 1;
+          s.n_fb64++;
+          s.sing = lu_factor<BS, double>(A64, n, lda, piv, red) != 0;
+        }
+      } else {
+        s.sing = lu_factor<BS, double>(A64, n, lda, piv, red) != 0;
+      }
+    }
+  }
+  const bool skip = lin && (!s.fin || s.sing);
+  if (!skip) {
+    // right-hand side of this round, formed in place of the residual
+    for (int i = threadIdx.x; i < n; i += BS) {
+      double v;
+      if (ph == PH_TS1) v = -G[i] / (kGamma * s.h);
+      else if (ph == PH_TS2) v = (-G[i] - 2.0 * M[i] * d[i]) / (kGamma * s.h);
+      else v = -G[i];
+      G[i] = v;
+    }
+    __syncthreads();
+    double *out = (ph == PH_NW_BASE || ph == PH_TS1) ? d : t;
+    solve_round<BS, MIXED>(c, o, s, G, out);
+    if (MIXED && s.sing) {  // an FP64 refactorisation found the matrix singular
+      if (ph == PH_NW_BASE) { start_ts<BS>(c, o, s); return; }
+      if (ph == PH_TS1) { s.n_lin += 2; reject_ts<BS>(c, o, s, true, 0.0); return; }
+      for (int i = threadIdx.x; i < n; i += BS) out[i] = __builtin_nan("");
+      __syncthreads();
+    }
+  }
+
+  switch (ph) {
+    case PH_NW_BASE: {
+      if (skip) { start_ts<BS>(c, o, s); return; }
+      s.n_lin++;
+      if (!all_finite<BS>(d, n, red)) { start_ts<BS>(c, o, s); return; }
+      const double nd = newton_norm<BS>(c, o, xnw, d, red);
+      s.nd = nd;
+      if (nd <= 1.0 && sres <= o.ftol) {
+        s.sres = sres;
+        step_clamped<BS>(c, o, xnw, 1.0, d, x);
+        finish<BS>(s, all_finite<BS>(x, n, red) ? RS_CONVERGED : RS_NONFINITE);
+        return;
+      }
+      double lam = 1.0;
+      if (c.energy) {
+        const double T = xnw[N], dT = d[N];
+        if (dT > 0.0 && T + dT > o.T_max) lam = (o.T_max - T) / dT;
+        if (dT < 0.0 && T + dT < o.T_min) lam = (T - o.T_min) / (-dT);
+      }
+      s.lam = lam;
+      try_trial<BS>(c, o, s);
+      return;
+    }
+    case PH_NW_TRIAL: {
+      s.n_lin++;
+      const double ndt = newton_norm<BS>(c, o, xnw, t, red);
+      if (ndt < s.nd) {
+        vcopy<BS>(xnw, xev, n);
+        s.nw_it++;
+        if (s.nw_it >= o.nw_max_it) { start_ts<BS>(c, o, s); return; }
+        if (s.n_lin >= o.max_lin) { finish<BS>(s, RS_MAXITER); return; }
+        s.phase = PH_NW_BASE;
+        vcopy<BS>(xev, xnw, n);
+      } else {
+        s.lam *= 0.5;
+        try_trial<BS>(c, o, s);
+      }
+      return;
+    }
+    case PH_TS1: {
+      if (skip) { s.n_lin += 2; reject_ts<BS>(c, o, s, true, 0.0); return; }
+      s.n_lin++;
+      for (int i = threadIdx.x; i < n; i += BS) {
+        double v = x[i] + s.h * d[i];
+        if (i == N) v = v < o.T_min ? o.T_min : (v > o.T_max ? o.T_max : v);
+        xev[i] = v;
+      }
+      __syncthreads();
+      s.phase = PH_TS2;
+      return;
+    }
+    case PH_TS2: {
+      s.n_lin++;
+      const double h = s.h;
+      double e2 = 0.0;
+      int bad = 0;
+      for (int i = threadIdx.x; i < n; i += BS) {
+        const double xn = x[i] + 1.5 * h * d[i] + 0.5 * h * t[i];
+        const double ax = fmax(fabs(x[i]), fabs(xn));
+        const double w = (i < N ? o.ts_atol_Y : o.ts_atol_T) + o.ts_rtol * ax;
+        const double e = 0.5 * h * (d[i] + t[i]) / w;
+        e2 += e * e;
+        bad |= !isfinite(xn);
+        if (i < N) bad |= xn < -o.ts_neg_tol;
+        else bad |= (xn < o.T_min || xn > o.T_max);
+        xev[i] = xn;
+      }
+      const double err = sqrt(block_sum<BS>(e2, red) / n);
+      const bool isbad = block_or<BS>(bad, red) || !isfinite(err);
+      if (!isbad && err <= 1.0) {
+        for (int i = threadIdx.x; i < n; i += BS) {
+          const double v = xev[i];
+          x[i] = (i < N && !(v > 0.0)) ? 0.0 : v;
+        }
+        __syncthreads();
+        double fac = 0.9 / sqrt(err > 1e-10 ? err : 1e-10);
+        s.h = h * (fac > 5.0 ? 5.0 : (fac < 0.2 ? 0.2 : fac));
+        if (s.h > o.h_max * c.tau) s.h = o.h_max * c.tau;
+        s.accepted++;
+        s.n_ts++;
+        if (s.accepted % o.nw_every == 0 && s.h >= o.nw_h_ratio * c.tau) start_attempt<BS>(c, o, s);
+        else start_ts<BS>(c, o, s);
+      } else {
+        reject_ts<BS>(c, o, s, isbad, err);
+      }
+      return;
+    }
+    default:
+      return;
+  }
+}
+
+// Initial controller state for x0 (Y projected onto Y >= 0).
+template <int BS>
+__device__ inline void init_state(const Ctx &c, const Opts &o, RState &s) {
+  s.phase = PH_NW_BASE;
+  s.status = RS_RUNNING;
+  s.n_lin = s.n_jac = s.n_ts = s.n_att = s.nw_it = s.accepted = 0;
+  s.fb64 = s.n_fb64 = s.sing = 0;
+  s.fin = 1;
+  s.nd = s.lam = s.sres = 0.0;
+  s.h = o.h0 * c.tau;
+  double *x = c.p(c.L.x);
+  for (int i = threadIdx.x; i < c.N; i += BS) x[i] = x[i] > 0.0 ? x[i] : 0.0;
+  __syncthreads();
+  start_attempt<BS>(c, o, s);
+}
+
+}  // namespace psr

@@ -1,0 +1,124 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/psr.h declares, and rejects invalid mechanisms before
+any device work."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "psr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(psr_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2005_11468_amd import _lib
+    return _lib.load()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("psr_create_mechanism", "psr_residual", "psr_solve_batch", "psr_jacobian",
+                 "psr_lu_factor_batch", "psr_lu_solve_batch", "psr_workspace_bytes",
+                 "psr_last_error", "psr_default_opts", "psr_destroy_mechanism",
+                 "psr_num_unknowns"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_default_opts_match_the_oracle(lib):
+    from oracle import oracle as O
+    import paper_2005_11468_amd as P
+    g = P.default_opts()
+    o = O.default_opts()
+    for name, _ in O.Opts._fields_:
+        assert getattr(g, name) == getattr(o, name), name
+    assert g.precision == P.PSR_FP64 and g.scheduler == P.PSR_PLAIN
+
+
+def _desc(mech):
+    from paper_2005_11468_amd import _lib
+    keep = {k: np.ascontiguousarray(v) for k, v in mech.items() if isinstance(v, np.ndarray)}
+    dpp = lambda x: x.astype(np.float64).ctypes.data_as(_lib.dp)
+    arrs = dict(ew=np.ascontiguousarray(mech["elem_weight"], np.float64),
+                se=np.ascontiguousarray(mech["species_elems"], np.int32),
+                nasa=np.ascontiguousarray(mech["nasa7"], np.float64),
+                ri=np.ascontiguousarray(mech["reac_idx"], np.int32),
+                rn=np.ascontiguousarray(mech["reac_nu"], np.int32),
+                pi=np.ascontiguousarray(mech["prod_idx"], np.int32),
+                pn=np.ascontiguousarray(mech["prod_nu"], np.int32),
+                A=np.ascontiguousarray(mech["A"], np.float64),
+                beta=np.ascontiguousarray(mech["beta"], np.float64),
+                Ea=np.ascontiguousarray(mech["Ea"], np.float64))
+    d = _lib.MechDesc(arrs["se"].shape[1], arrs["se"].shape[0], arrs["ri"].shape[0],
+                      arrs["ew"].ctypes.data_as(_lib.dp), arrs["se"].ctypes.data_as(_lib.ip),
+                      arrs["nasa"].ctypes.data_as(_lib.dp), 300.0, 3000.0,
+                      arrs["ri"].ctypes.data_as(_lib.ip), arrs["rn"].ctypes.data_as(_lib.ip),
+                      arrs["pi"].ctypes.data_as(_lib.ip), arrs["pn"].ctypes.data_as(_lib.ip),
+                      arrs["A"].ctypes.data_as(_lib.dp), arrs["beta"].ctypes.data_as(_lib.dp),
+                      arrs["Ea"].ctypes.data_as(_lib.dp))
+    return d, arrs
+
+
+def _create(lib, mech):
+    d, keep = _desc(mech)
+    h = C.c_void_p()
+    st = lib.psr_create_mechanism(C.byref(d), C.byref(h))
+    return st, lib.psr_last_error().decode()
+
+
+def test_rejects_unbalanced_reaction(lib):
+    from tests import tiny_mechs as tm
+    m = tm.association()
+    m["reac_idx"][0] = [0, -1, -1]  # 2 A -> C: two carbons in, one out, no hydrogen in
+    m["reac_nu"][0] = [2, 0, 0]
+    st, msg = _create(lib, m)
+    assert st == 1 and "balanced" in msg
+
+
+def test_rejects_species_on_both_sides(lib):
+    from tests import tiny_mechs as tm
+    m = tm.association()
+    m["prod_idx"][0, :2] = [2, 0]
+    m["prod_nu"][0, :2] = [1, 1]
+    st, msg = _create(lib, m)
+    assert st == 1 and "both sides" in msg
+
+
+def test_rejects_bad_index_and_coefficients(lib):
+    from tests import tiny_mechs as tm
+    m = tm.association()
+    m["reac_idx"][0, 0] = 7
+    st, msg = _create(lib, m)
+    assert st == 1 and "out of range" in msg
+    m = tm.association()
+    m["reac_nu"][0, 0] = 0
+    st, msg = _create(lib, m)
+    assert st == 1 and "coefficient" in msg
+    m = tm.association()
+    m["A"][0] = -1.0
+    st, msg = _create(lib, m)
+    assert st == 1 and "Arrhenius" in msg
+
+
+def test_rejects_null_and_empty(lib):
+    h = C.c_void_p()
+    assert lib.psr_create_mechanism(None, C.byref(h)) == 1
+    from paper_2005_11468_amd import _lib
+    o = _lib.SolveOpts()
+    lib.psr_default_opts(C.byref(o))
+    assert lib.psr_workspace_bytes(None, 0, C.byref(o)) == 0
+    assert lib.psr_solve_batch(None, 0, C.byref(o), None, 0, None, None) == 1
+    o.precision = 7
+    assert lib.psr_solve_batch(None, 0, C.byref(o), None, 0, None, None) == 1

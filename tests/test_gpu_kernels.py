@@ -1,0 +1,129 @@
+"""GPU parity of the rate/residual, Jacobian and LU kernels against the
+oracle, element by element, on seeded inputs (called through the C ABI)."""
+import numpy as np
+import pytest
+
+from tests import tiny_mechs as tm
+from tests.gpu_util import cond_dev, dev
+
+pytestmark = pytest.mark.gpu
+
+PATM = 101325.0
+
+
+def _random_states(n_sp, B, energy, seed):
+    rng = np.random.default_rng(seed)
+    Y = rng.dirichlet(np.full(n_sp, 0.4), B).T
+    if energy:
+        return np.concatenate([Y, rng.uniform(600, 2800, (1, B))], axis=0)
+    return Y
+
+
+def _cases():
+    from psr_inputs import workload
+    out = []
+    for name, B in (("isothermal", 16), ("energy", 257)):
+        mech, cond, _, energy = workload(name, B)
+        out.append((name, mech, cond, energy))
+    mech = tm.small_network()
+    rng = np.random.default_rng(4)
+    B = 70
+    cond = {"P": np.full(B, PATM), "tau": np.exp(rng.uniform(np.log(1e-5), 0, B)),
+            "T_in": rng.uniform(300, 900, B), "Y_in": rng.dirichlet(np.ones(5), B).T.copy()}
+    out.append(("small_iso", mech, cond, False))
+    out.append(("small_energy", mech, cond, True))
+    return out
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2005_11468_amd as P
+    return P
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_residual_matches_oracle(gpu, oracle_mod, case):
+    name, mech, cond, energy = _cases()[case]
+    M = gpu.Mechanism(mech)
+    O = oracle_mod.Mechanism(mech)
+    N = M.n_species
+    B = cond["P"].shape[0]
+    x = _random_states(N, B, energy, 10 + case)
+    import torch
+    sc = torch.empty(B, dtype=torch.float64, device="cuda:0")
+    F = gpu.residual(M, cond_dev(cond), energy, dev(x), scaled=sc).cpu().numpy()
+    sc = sc.cpu().numpy()
+    for b in range(B):
+        args = (cond["P"][b], cond["tau"][b], cond["T_in"][b], cond["Y_in"][:, b], energy, x[:, b])
+        Fo = O.residual(*args)
+        scale = np.abs(Fo).max()
+        np.testing.assert_allclose(F[:, b], Fo, rtol=1e-10, atol=1e-12 * scale, err_msg=f"{name} b={b}")
+        so = O.scaled_residual(*args)
+        np.testing.assert_allclose(sc[b], so, rtol=1e-8, err_msg=f"{name} b={b}")
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_jacobian_matches_oracle(gpu, oracle_mod, case):
+    name, mech, cond, energy = _cases()[case]
+    M = gpu.Mechanism(mech)
+    O = oracle_mod.Mechanism(mech)
+    N = M.n_species
+    B = min(cond["P"].shape[0], 40)
+    cond = {k: np.ascontiguousarray(v[..., :B]) for k, v in cond.items()}
+    x = _random_states(N, B, energy, 20 + case)
+    J = gpu.jacobian(M, cond_dev(cond), energy, dev(x)).cpu().numpy()
+    for b in range(B):
+        Jo = O.jacobian(cond["P"][b], cond["tau"][b], cond["T_in"][b], cond["Y_in"][:, b], energy,
+                        x[:, b])
+        scale = np.abs(Jo).max(axis=1, keepdims=True)
+        bad = np.abs(J[b] - Jo) > 1e-10 * np.abs(Jo) + 1e-13 * scale
+        assert not bad.any(), (name, b, np.argwhere(bad)[:4])
+
+
+@pytest.mark.parametrize("n", [1, 3, 17, 54, 64, 65, 101])
+def test_lu_fp64_matches_oracle(gpu, oracle_mod, n):
+    rng = np.random.default_rng(300 + n)
+    B = 13
+    A = rng.standard_normal((B, n, n))
+    LU, piv, info = gpu.lu_factor_batch(dev(A.copy()))
+    LU, piv, info = LU.cpu().numpy(), piv.cpu().numpy(), info.cpu().numpy()
+    assert np.all(info == 0)
+    for b in range(B):
+        lo, po, io = oracle_mod.lu_factor(A[b])
+        np.testing.assert_array_equal(piv[b], po)
+        np.testing.assert_allclose(LU[b], lo, rtol=1e-10, atol=1e-12 * np.abs(A[b]).max())
+    rhs = rng.standard_normal((B, n))
+    z = gpu.lu_solve_batch(dev(LU), dev(piv), dev(rhs.copy())).cpu().numpy()
+    for b in range(B):
+        zo = oracle_mod.lu_solve(LU[b], piv[b], rhs[b])
+        np.testing.assert_allclose(z[b], zo, rtol=1e-9, atol=1e-12 * np.abs(zo).max())
+
+
+def test_lu_singular_info(gpu):
+    A = np.zeros((3, 4, 4))
+    A[0] = np.eye(4)
+    A[1] = np.eye(4)
+    A[1, 2, 2] = 0.0
+    A[2, :, 1] = 0.0
+    A[2] += np.diag([1.0, 0.0, 1.0, 1.0])
+    _, _, info = gpu.lu_factor_batch(dev(A))
+    assert info.cpu().numpy().tolist() == [0, 3, 2]
+
+
+@pytest.mark.parametrize("n", [5, 54])
+def test_lu_float_factors_backward_error(gpu, n):
+    rng = np.random.default_rng(700 + n)
+    B = 9
+    A = rng.standard_normal((B, n, n)) + n * np.eye(n)[None]
+    LU, piv, info = gpu.lu_factor_batch(dev(A.copy()), precision=gpu.PSR_MIXED)
+    LU, piv = LU.cpu().numpy(), piv.cpu().numpy()
+    for b in range(B):
+        L = np.tril(LU[b], -1) + np.eye(n)
+        U = np.triu(LU[b])
+        PA = A[b].copy()
+        for k in range(n):
+            PA[[k, piv[b, k]]] = PA[[piv[b, k], k]]
+        err = np.abs(L @ U - PA).max() / np.abs(A[b]).max()
+        assert err <= 4 * n * np.finfo(np.float32).eps
