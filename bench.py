@@ -1,0 +1,169 @@
+"""Benchmark: converged PSR reactor-solves per second on one MI355X.
+
+Workload: the 53-species / 325-reaction synthetic mechanism with energy
+equation, 16384 reactors (the mixed-precision workload; seeded inputs from
+psr_inputs).  One step = one psr_solve_batch call that solves the whole batch
+from the same initial guess, with inputs already resident in HBM.
+
+Printed JSON line (one): the mixed-precision persistent solver's rate as
+`value`, the plain FP64 host-driven solver on the same inputs beside it, a
+roofline object for the dominant kernel, parity against the oracle on the
+CPU-baseline sample, and the oracle's own throughput on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_ALU_TFLOPS = 78.6   # FP64 vector = non-packed FP32 vector: 256 CU x 64 FMA/clk x 2 x 2.4 GHz
+TOL = {0: 1e-8, 1: 1e-7}
+
+
+def alg_flops(n, N, I):
+    """Algorithmic flops of one linearisation (Jacobian + LU) and of one
+    round (residual + triangular solves), counting an exp/log as one op."""
+    lin = 2.0 / 3.0 * n ** 3 + 90.0 * I + 10.0 * N * N
+    rnd = 32.0 * I + 32.0 * N + 2.0 * n * n
+    return lin, rnd
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="mixed")
+    ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="reactors for the oracle baseline (0: 384 per host core)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import paper_2005_11468_amd as P
+    from psr_inputs import workload
+    from tests.gpu_util import cond_dev, dev, rel_err
+
+    mech, cond, x0, energy = workload(args.workload)
+    B = x0.shape[1]
+    N = mech["species_elems"].shape[0]
+    n = x0.shape[0]
+    I = mech["A"].shape[0]
+    M = P.Mechanism(mech)
+    cd = cond_dev(cond)
+    x0d = dev(x0)
+    x = x0d.clone()
+    status = torch.empty(B, dtype=torch.int32, device="cuda:0")
+    nlin = torch.empty(B, dtype=torch.int32, device="cuda:0")
+    group = [dict(mech=M, cond=cd, energy=energy, x=x, status=status, n_lin=nlin)]
+    stream = torch.cuda.current_stream()
+
+    def run(opts, steps, warmup, ws=None):
+        for _ in range(warmup):
+            x.copy_(x0d)
+            _, ws = P.solve_batch(group, opts, workspace=ws, stats=False)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            x.copy_(x0d)
+            _, ws = P.solve_batch(group, opts, workspace=ws, stats=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1) / steps
+        # one more solve for the solver statistics (kernel time from HIP events
+        # recorded by the library on this stream around its launches)
+        x.copy_(x0d)
+        st, ws = P.solve_batch(group, opts, workspace=ws, stats=True)
+        torch.cuda.synchronize()
+        return ms, wall / steps, st, ws
+
+    mixed = P.default_opts(precision=P.PSR_MIXED, scheduler=P.PSR_PERSISTENT)
+    ms_mixed, wall_mixed, st_mixed, ws = run(mixed, args.steps, args.warmup)
+    x_mixed = x.cpu().numpy()
+    s_mixed = status.cpu().numpy()
+    n_mixed = nlin.cpu().numpy()
+
+    plain = P.default_opts(precision=P.PSR_FP64, scheduler=P.PSR_PLAIN)
+    ms_plain, wall_plain, st_plain, _ = run(plain, args.plain_steps, 0)
+    x_plain = x.cpu().numpy()
+    s_plain = status.cpu().numpy()
+
+    # oracle on a bounded sample: CPU baseline and parity reference
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        cores = min(os.cpu_count() or 1, 16)
+        S = args.cpu_sample or min(B, 384 * cores)
+        idx = np.sort(np.random.default_rng(2024).choice(B, S, replace=False))
+        t0 = time.perf_counter()
+        xo, so = O.solve_batch(mech, cond, x0, energy, idx=idx, processes=cores)
+        tcpu = time.perf_counter() - t0
+        conv_o = so["status"] == 0
+        cpu = {"value": float(conv_o.sum() / tcpu), "unit": "reactor-solves/s", "cores": cores,
+               "kind": "oracle",
+               "sample": f"{S} of {B} reactors (seeded), single-threaded FP64 C oracle, "
+                         f"one process per core, {tcpu:.1f} s"}
+        both = conv_o & (s_mixed[idx] == 0)
+        em = rel_err(x_mixed[:, idx][:, both], xo[:, both], N)
+        bp = conv_o & (s_plain[idx] == 0)
+        ep = rel_err(x_plain[:, idx][:, bp], xo[:, bp], N)
+        parity = {"sample": int(S), "oracle_converged": int(conv_o.sum()),
+                  "mixed_max_rel_err": float(em.max()) if em.size else None,
+                  "mixed_within_1e-7": float((em <= TOL[1]).mean()) if em.size else 0.0,
+                  "fp64_max_rel_err": float(ep.max()) if ep.size else None,
+                  "fp64_within_1e-8": float((ep <= TOL[0]).mean()) if ep.size else 0.0}
+
+    conv_mixed = int((s_mixed == 0).sum())
+    conv_plain = int((s_plain == 0).sum())
+    frac_m = parity["mixed_within_1e-7"] if parity else 1.0
+    frac_p = parity["fp64_within_1e-8"] if parity else 1.0
+    value = conv_mixed * frac_m / (ms_mixed / 1e3)
+    value_plain = conv_plain * frac_p / (ms_plain / 1e3)
+
+    lin_f, rnd_f = alg_flops(n, N, I)
+    flops = st_mixed.jac_total * lin_f + st_mixed.lin_total * rnd_f
+    achieved = flops / (st_mixed.kernel_ms / 1e3) / 1e12
+    out = {
+        "metric": "converged PSR solves/sec (1 GPU), mixed-prec batched vs plain FP64, rel err<=1e-7",
+        "value": value, "unit": "reactor-solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_mixed, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": "mixed: 53 species / 325 reactions + energy, 16384 reactors",
+                   "reactors": B, "species": N, "reactions": I, "unknowns": n,
+                   "precision": "mixed (FP32 LU + FP64 refinement, FP64 residual)",
+                   "scheduler": "persistent work queue"},
+        "fp64_plain": {"value": value_plain, "ms_per_step": ms_plain,
+                       "converged": conv_plain, "rounds": st_plain.rounds,
+                       "speedup_mixed_over_plain": value / value_plain if value_plain else None},
+        "solver": {"converged": conv_mixed, "reactors": B, "lin_total": st_mixed.lin_total,
+                   "lin_max": st_mixed.lin_max, "jac_total": st_mixed.jac_total,
+                   "fp64_fallbacks": st_mixed.fp64_fallbacks, "wall_ms_per_step": wall_mixed * 1e3},
+        "roofline": {"kernel": "k_persistent<mixed>", "bound": "alu", "achieved": achieved,
+                     "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
+                     "traffic": None, "kernel_ms": st_mixed.kernel_ms,
+                     "alg_flops": flops},
+        "parity": parity,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
