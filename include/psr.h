@@ -142,6 +142,11 @@ typedef struct {
   int32_t max_lin;             /* per-reactor linear-solve budget               */
   /* mixed precision */
   int32_t max_refine;          /* refinement sweeps per solve before FP64 fallback */
+  /* kernel engine: 0 automatic (wavefront engine when n <= 64 and the
+   * mechanism fits its LDS, else one workgroup per reactor), 1 one workgroup
+   * of 256 threads per reactor, 2 one wavefront per reactor (PSR_EUNSUPPORTED
+   * if it does not fit). Results agree to rounding, not bitwise. */
+  int32_t engine;
 } psr_solve_opts;
 
 /* Fill opts with the defaults (FP64, plain scheduler, tolerances above). */

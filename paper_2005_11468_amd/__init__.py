@@ -65,14 +65,15 @@ class Mechanism:
         h = C.c_void_p()
         _lib.check(L.psr_create_mechanism(C.byref(desc), C.byref(h)), "psr_create_mechanism")
         self.handle = h
+        self._L = L  # keeps the library reachable for __del__ at interpreter exit
 
     def n_unknowns(self, energy: bool) -> int:
         return int(_lib.load().psr_num_unknowns(self.handle, 1 if energy else 0))
 
     def __del__(self):
-        h = getattr(self, "handle", None)
-        if h is not None and _lib._lib is not None:
-            _lib._lib.psr_destroy_mechanism(h)
+        h, lib = getattr(self, "handle", None), getattr(self, "_L", None)
+        if h is not None and lib is not None:
+            lib.psr_destroy_mechanism(h)
             self.handle = None
 
 

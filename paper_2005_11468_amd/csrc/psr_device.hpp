@@ -28,6 +28,7 @@ struct MechDev {
   const int *dnu;                  // [I] sum of net coefficients
   const int *r_idx, *r_nu, *p_idx, *p_nu;  // [I*3], -1 pads
   const int *sp_ptr, *sp_rx, *sp_nu;       // species -> (reaction, net nu), CSR
+  const int *packed;  // wavefront engine: w0[I], w1[I], w2[I], CSR entries[nnz]; null if unusable
 };
 
 struct Opts {

@@ -23,6 +23,7 @@
 
 #include "../../include/psr.h"
 #include "psr_solver.hpp"
+#include "psr_wave_solver.hpp"
 
 using namespace psr;
 
@@ -234,6 +235,162 @@ __global__ void k_zero_int(int *p, int n) {
   if (i < n) p[i] = 0;
 }
 
+
+// ------------------------------------------------- wavefront-per-reactor engine
+
+namespace wk {
+using namespace psr::wave;
+
+__host__ __device__ inline size_t align16(size_t v) { return (v + 15) / 16 * 16; }
+
+// Doubles of one reactor's HBM area for the plain scheduler (lane-interleaved).
+template <int NP, bool MIXED>
+__host__ __device__ inline int plain_stride(int n) {
+  return 10 * WS + NP * WS + (MIXED ? n * WArea<NP>::ldj_of(n) : 0);
+}
+
+template <int NP, bool MIXED>
+__device__ inline void make_wctx(WCtx &c, const Tables &t, const GroupDev &g, int64_t b) {
+  const int lane = lane_id();
+  c.t = t;
+  c.N = g.m.N;
+  c.n = g.m.N + (g.energy ? 1 : 0);
+  c.energy = g.energy;
+  c.P = g.P[b];
+  c.tau = g.tau[b];
+  c.Tin = g.Tin[b];
+  c.Yin = lane < c.N ? g.Yin[(int64_t)lane * g.B + b] : 0.0;
+  c.Hin = lane < c.N ? inlet_enthalpy(t, lane, c.Tin) : 0.0;
+}
+
+template <int NP, bool MIXED>
+__device__ inline void write_result_w(const GroupDev &g, const WCtx &c, const WState<NP, MIXED> &r,
+                                      RState *states, int64_t b) {
+  const int lane = lane_id();
+  if (lane < c.n) g.x[(int64_t)lane * g.B + b] = r.x;
+  if (lane == 0) {
+    g.status[b] = r.s.status;
+    if (g.nlin) g.nlin[b] = r.s.n_lin;
+    states[b] = r.s;
+  }
+}
+
+// Persistent scheduler: each wavefront pulls reactor indices from the device
+// queue and solves each reactor to completion; the workgroup's wavefronts
+// share the LDS copy of the mechanism tables.
+template <int NP, bool MIXED>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) k_wpersist(GroupDev g, Opts o, RState *states, int *queue) {
+  extern __shared__ double lds[];
+  char *base = reinterpret_cast<char *>(lds);
+  const Tables t = stage_tables(g.m, base, g.m.packed);
+  __syncthreads();
+  const int n = g.m.N + (g.energy ? 1 : 0);
+  const size_t toff = align16(tables_bytes(g.m.N, g.m.I, g.m.nnz));
+  WArea<NP> A;
+  A.at(reinterpret_cast<double *>(base + toff) + (size_t)wave_id() * WArea<NP>::doubles(n), n);
+  const int lane = lane_id();
+  for (;;) {
+    int b = 0;
+    if (lane == 0) b = atomicAdd(queue, 1);
+    b = bcast(b, 0);
+    if (b >= g.B) break;
+    WCtx c;
+    make_wctx<NP, MIXED>(c, t, g, b);
+    WState<NP, MIXED> r;
+    init_w<NP, MIXED>(c, o, r, lane < n ? g.x[(int64_t)lane * g.B + b] : 0.0);
+    while (r.s.phase != PH_DONE) w_round<NP, MIXED>(c, A, o, r);
+    write_result_w<NP, MIXED>(g, c, r, states, b);
+  }
+}
+
+template <int NP, bool MIXED>
+__device__ inline void save_w(const WCtx &c, const WArea<NP> &A, const WState<NP, MIXED> &r, double *ar) {
+  const int lane = lane_id(), n = c.n;
+  const double v[9] = {r.x, r.xnw, r.xev, r.d, r.t, r.M, r.rs, r.cs, r.piv};
+#pragma unroll
+  for (int q = 0; q < 9; q++) ar[q * WS + lane] = v[q];
+  int *ints = reinterpret_cast<int *>(ar + 9 * WS);
+  ints[lane] = r.pos;
+  ints[WS + lane] = r.perm;
+  double *fac = ar + 10 * WS;
+  if (r.s.phase == PH_NW_TRIAL || r.s.phase == PH_TS2) {  // factors still in use
+#pragma unroll
+    for (int j = 0; j < NP; j++)
+      if (j < n) fac[j * WS + lane] = r.a[j];
+    if (MIXED && !r.s.fb64) {  // refinement needs the FP64 matrix
+      double *Jc = fac + NP * WS;
+      for (int e = lane; e < n * A.ldj; e += WS) Jc[e] = A.J[e];
+    }
+  }
+}
+
+template <int NP, bool MIXED>
+__device__ inline void load_w(const WCtx &c, const WArea<NP> &A, WState<NP, MIXED> &r, const double *ar) {
+  const int lane = lane_id(), n = c.n;
+  r.x = ar[lane]; r.xnw = ar[WS + lane]; r.xev = ar[2 * WS + lane]; r.d = ar[3 * WS + lane];
+  r.t = ar[4 * WS + lane]; r.M = ar[5 * WS + lane]; r.rs = ar[6 * WS + lane]; r.cs = ar[7 * WS + lane];
+  r.piv = ar[8 * WS + lane];
+  const int *ints = reinterpret_cast<const int *>(ar + 9 * WS);
+  r.pos = ints[lane];
+  r.perm = ints[WS + lane];
+  const double *fac = ar + 10 * WS;
+#pragma unroll
+  for (int j = 0; j < NP; j++) r.a[j] = 0.0;
+  if (r.s.phase == PH_NW_TRIAL || r.s.phase == PH_TS2) {
+#pragma unroll
+    for (int j = 0; j < NP; j++)
+      if (j < n) r.a[j] = fac[j * WS + lane];
+    if (MIXED && !r.s.fb64) {
+      const double *Jc = fac + NP * WS;
+      for (int e = lane; e < n * A.ldj; e += WS) A.J[e] = Jc[e];
+    }
+  }
+  wsync();
+}
+
+// Plain scheduler on the wavefront engine: one controller round per launch,
+// each reactor's vectors (and, while a linearisation is in use, its factors)
+// kept in HBM between launches.
+template <int NP, bool MIXED, bool FIRST>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) k_wround(GroupDev g, Opts o, RState *states, double *area,
+                                                int stride, int rpw, int *active) {
+  extern __shared__ double lds[];
+  char *base = reinterpret_cast<char *>(lds);
+  const Tables t = stage_tables(g.m, base, g.m.packed);
+  __syncthreads();
+  const int n = g.m.N + (g.energy ? 1 : 0);
+  const int64_t b = (int64_t)blockIdx.x * rpw + wave_id();
+  if (b >= g.B) return;
+  RState s0 = states[b];
+  if (!FIRST && s0.phase == PH_DONE) return;
+  const size_t toff = align16(tables_bytes(g.m.N, g.m.I, g.m.nnz));
+  WArea<NP> A;
+  A.at(reinterpret_cast<double *>(base + toff) + (size_t)wave_id() * WArea<NP>::doubles(n), n);
+  const int lane = lane_id();
+  WCtx c;
+  make_wctx<NP, MIXED>(c, t, g, b);
+  WState<NP, MIXED> r;
+  double *ar = area + b * (int64_t)stride;
+  if (FIRST) {
+    init_w<NP, MIXED>(c, o, r, lane < n ? g.x[(int64_t)lane * g.B + b] : 0.0);
+  } else {
+    r.s = s0;
+    load_w<NP, MIXED>(c, A, r, ar);
+    w_round<NP, MIXED>(c, A, o, r);
+  }
+  if (r.s.phase == PH_DONE) {
+    write_result_w<NP, MIXED>(g, c, r, states, b);
+  } else {
+    save_w<NP, MIXED>(c, A, r, ar);
+    if (lane == 0) {
+      states[b] = r.s;
+      atomicAdd(active, 1);
+    }
+  }
+}
+
+}  // namespace wk
+
 // ------------------------------------------------------------ host: mechanism
 
 extern "C" const char *psr_last_error(void) { return g_err.c_str(); }
@@ -261,6 +418,7 @@ extern "C" void psr_default_opts(psr_solve_opts *o) {
   o->nw_every = 10;
   o->max_lin = 1000;
   o->max_refine = 6;
+  o->engine = 0;
 }
 
 extern "C" psr_status psr_create_mechanism(const psr_mech_desc *d, psr_mech_t *out) {
@@ -336,7 +494,28 @@ extern "C" psr_status psr_create_mechanism(const psr_mech_desc *d, psr_mech_t *o
   const int nnz = ptr[N];
   // one blob: doubles first, then ints
   const size_t nd = (size_t)N + 7 * N + 3 * I;
-  const size_t ni = (size_t)I + 12 * I + (N + 1) + 2 * std::max(nnz, 1);
+  // packed slot words for the wavefront engine (needs N <= 254, nu <= 15)
+  bool packable = N <= 254;
+  std::vector<int> pk(3 * (size_t)I + nnz, 0);
+  for (int k = 0; k < I && packable; k++) {
+    int w0 = 0, w1 = 0, w2 = 0;
+    for (int s = 0; s < 3; s++) {
+      const int ir = ridx[3 * k + s], ip = pidx[3 * k + s];
+      w0 |= (ir >= 0 ? ir : 0xff) << (8 * s);
+      w1 |= (ip >= 0 ? ip : 0xff) << (8 * s);
+      if (rnu[3 * k + s] > 15 || pnu[3 * k + s] > 15) packable = false;
+      w2 |= (rnu[3 * k + s] & 0xf) << (4 * s);
+      w2 |= (pnu[3 * k + s] & 0xf) << (12 + 4 * s);
+    }
+    if (dnu[k] < -16 || dnu[k] > 100) packable = false;
+    w2 |= ((dnu[k] + 16) & 0xff) << 24;
+    pk[k] = w0; pk[I + k] = w1; pk[2 * I + k] = w2;
+  }
+  for (int e = 0; e < nnz && packable; e++) {
+    if (rx[e] >= (1 << 23) || nu[e] < -127 || nu[e] > 127) packable = false;
+    pk[3 * (size_t)I + e] = (rx[e] << 8) | ((nu[e] + 128) & 0xff);
+  }
+  const size_t ni = (size_t)I + 12 * I + (N + 1) + 2 * std::max(nnz, 1) + pk.size();
   std::vector<char> host(nd * 8 + ni * 4);
   double *hd = reinterpret_cast<double *>(host.data());
   int *hi = reinterpret_cast<int *>(host.data() + nd * 8);
@@ -348,6 +527,7 @@ extern "C" psr_status psr_create_mechanism(const psr_mech_desc *d, psr_mech_t *o
   const size_t odnu = puti(dnu.data(), I), orI = puti(ridx.data(), 3 * I), orN = puti(rnu.data(), 3 * I);
   const size_t opI = puti(pidx.data(), 3 * I), opN = puti(pnu.data(), 3 * I);
   const size_t optr = puti(ptr.data(), N + 1), orx = puti(rx.data(), nnz), onu = puti(nu.data(), nnz);
+  const size_t opk = puti(pk.data(), pk.size());
   for (int i = 0; i < N * 7; i++)
     if (!std::isfinite(d->nasa7[i])) return fail(PSR_EINVAL, "non-finite NASA-7 coefficient");
   void *blob = nullptr;
@@ -366,6 +546,7 @@ extern "C" psr_status psr_create_mechanism(const psr_mech_desc *d, psr_mech_t *o
   m->dev.dnu = bi + odnu; m->dev.r_idx = bi + orI; m->dev.r_nu = bi + orN;
   m->dev.p_idx = bi + opI; m->dev.p_nu = bi + opN;
   m->dev.sp_ptr = bi + optr; m->dev.sp_rx = bi + orx; m->dev.sp_nu = bi + onu;
+  m->dev.packed = packable ? bi + opk : nullptr;
   *out = m;
   return PSR_OK;
 }
@@ -472,6 +653,105 @@ static Opts to_dev_opts(const psr_solve_opts *o) {
 
 static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
+// Wavefront engine choice: NP (register row length) for n unknowns, or 0.
+static int wave_np(int n) { return n <= 16 ? 16 : (n <= 32 ? 32 : (n <= 64 ? 64 : 0)); }
+
+struct WavePlan {
+  int NP = 0, rpw = 0;
+  size_t lds = 0;
+  int stride = 0;  // plain scheduler area, doubles per reactor
+};
+
+static WavePlan wave_plan(psr_mech_t m, int energy, bool mixed, int engine) {
+  WavePlan w;
+  const int n = m->N + (energy ? 1 : 0);
+  if (engine == 1 || !m->dev.packed) return w;
+  const int NP = wave_np(n);
+  if (!NP) return w;
+  const size_t tb = wk::align16(psr::wave::tables_bytes(m->N, m->I, m->nnz));
+  size_t per = 0;
+  switch (NP) {
+    case 16: per = (size_t)psr::wave::WArea<16>::doubles(n) * 8; break;
+    case 32: per = (size_t)psr::wave::WArea<32>::doubles(n) * 8; break;
+    default: per = (size_t)psr::wave::WArea<64>::doubles(n) * 8; break;
+  }
+  const size_t lim = (size_t)lds_limit_bytes();
+  for (int rpw = 4; rpw >= 1; rpw /= 2) {
+    if (tb + rpw * per <= lim) {
+      w.NP = NP;
+      w.rpw = rpw;
+      w.lds = tb + rpw * per;
+      break;
+    }
+  }
+  if (!w.NP) return w;
+  switch (NP) {
+    case 16: w.stride = mixed ? wk::plain_stride<16, true>(n) : wk::plain_stride<16, false>(n); break;
+    case 32: w.stride = mixed ? wk::plain_stride<32, true>(n) : wk::plain_stride<32, false>(n); break;
+    default: w.stride = mixed ? wk::plain_stride<64, true>(n) : wk::plain_stride<64, false>(n); break;
+  }
+  return w;
+}
+
+template <int NP, bool MIXED>
+static psr_status launch_wave(const GroupDev &gd, const Opts &od, const WavePlan &w, int scheduler,
+                              RState *states, int *counters, double *area, hipStream_t stream,
+                              int max_rounds, int *rounds_out) {
+  const int64_t B = gd.B;
+  const int threads = 64 * w.rpw;
+  if (scheduler == PSR_PERSISTENT) {
+    int dev = 0, ncu = 0, per_cu = 0;
+    HIP_OK(hipGetDevice(&dev));
+    HIP_OK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wk::k_wpersist<NP, MIXED>, threads, w.lds));
+    if (per_cu < 1) per_cu = 1;
+    const int64_t need = (B + w.rpw - 1) / w.rpw;
+    const int64_t grid = std::min<int64_t>(need, (int64_t)ncu * per_cu);
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, counters, 64);
+    hipLaunchKernelGGL((wk::k_wpersist<NP, MIXED>), dim3((unsigned)grid), dim3(threads), w.lds, stream, gd, od,
+                       states, counters);
+    HIP_OK(hipGetLastError());
+    *rounds_out = 0;
+    return PSR_OK;
+  }
+  const unsigned grid = (unsigned)((B + w.rpw - 1) / w.rpw);
+  hipLaunchKernelGGL((wk::k_wround<NP, MIXED, true>), dim3(grid), dim3(threads), w.lds, stream, gd, od, states,
+                     area, w.stride, w.rpw, counters);
+  HIP_OK(hipGetLastError());
+  int active = 1, rounds = 0;
+  const int check_every = 4;
+  while (active > 0 && rounds < max_rounds) {
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, counters, 1);
+    for (int r = 0; r < check_every; r++) {
+      hipLaunchKernelGGL((wk::k_wround<NP, MIXED, false>), dim3(grid), dim3(threads), w.lds, stream, gd, od,
+                         states, area, w.stride, w.rpw, counters);
+      rounds++;
+    }
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(&active, counters, sizeof(int), hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipStreamSynchronize(stream));
+  }
+  *rounds_out = rounds;
+  if (active > 0) return fail(PSR_EDEVICE, "plain scheduler did not retire every reactor");
+  return PSR_OK;
+}
+
+static psr_status run_wave(const GroupDev &gd, const Opts &od, const WavePlan &w, bool mixed, int scheduler,
+                           RState *states, int *counters, double *area, hipStream_t stream, int max_rounds,
+                           int *rounds) {
+  switch (w.NP) {
+    case 16:
+      return mixed ? launch_wave<16, true>(gd, od, w, scheduler, states, counters, area, stream, max_rounds, rounds)
+                   : launch_wave<16, false>(gd, od, w, scheduler, states, counters, area, stream, max_rounds, rounds);
+    case 32:
+      return mixed ? launch_wave<32, true>(gd, od, w, scheduler, states, counters, area, stream, max_rounds, rounds)
+                   : launch_wave<32, false>(gd, od, w, scheduler, states, counters, area, stream, max_rounds, rounds);
+    default:
+      return mixed ? launch_wave<64, true>(gd, od, w, scheduler, states, counters, area, stream, max_rounds, rounds)
+                   : launch_wave<64, false>(gd, od, w, scheduler, states, counters, area, stream, max_rounds, rounds);
+  }
+}
+
 // Workspace of one group: states [B], plain-scheduler areas [B][persist],
 // counters.
 static size_t group_ws(const psr_group &g, const psr_solve_opts *o) {
@@ -479,7 +759,9 @@ static size_t group_ws(const psr_group &g, const psr_solve_opts *o) {
   const bool mixed = o->precision == PSR_MIXED;
   L.make(g.mech->N, g.mech->I, g.mech->N + (g.cond.energy ? 1 : 0), mixed, kBS);
   size_t bytes = align256(sizeof(RState) * (size_t)g.cond.n_reactors) + 256;
-  if (o->scheduler == PSR_PLAIN) bytes += align256((size_t)L.persist * 8 * g.cond.n_reactors);
+  const WavePlan w = wave_plan(g.mech, g.cond.energy, mixed, o->engine);
+  if (o->scheduler == PSR_PLAIN)
+    bytes += align256((size_t)(w.NP ? w.stride : L.persist) * 8 * g.cond.n_reactors);
   return bytes;
 }
 
@@ -501,10 +783,11 @@ static psr_status check_opts(const psr_solve_opts *o) {
   if (!(o->rtol > 0) || !(o->atol_Y >= 0) || !(o->atol_T >= 0) || !(o->ftol > 0) ||
       !(o->lambda_min > 0 && o->lambda_min <= 1) || !(o->T_min < o->T_max) || !(o->ts_rtol > 0) ||
       !(o->h0 > 0) || !(o->h_min > 0) || !(o->h_max > 0) || o->nw_max_it < 1 || o->nw_every < 1 ||
-      o->max_lin < 1 || o->max_refine < 0)
+      o->max_lin < 1 || o->max_refine < 0 || o->engine < 0 || o->engine > 2)
     return fail(PSR_EINVAL, "option out of range");
   return PSR_OK;
 }
+
 
 static psr_status solve_group(const psr_group &g, const psr_solve_opts *o, void *ws, hipStream_t stream,
                               psr_solve_stats *acc) {
@@ -513,7 +796,10 @@ static psr_status solve_group(const psr_group &g, const psr_solve_opts *o, void 
   Layout L;
   L.make(g.mech->N, g.mech->I, g.mech->N + (g.cond.energy ? 1 : 0), mixed, kBS);
   const size_t lds = (size_t)L.total * 8;
-  if (lds > (size_t)lds_limit_bytes())
+  const WavePlan wplan = wave_plan(g.mech, g.cond.energy, mixed, o->engine);
+  if (o->engine == 2 && !wplan.NP)
+    return fail(PSR_EUNSUPPORTED, "wavefront engine needs n <= 64 and a mechanism that fits its LDS");
+  if (!wplan.NP && lds > (size_t)lds_limit_bytes())
     return fail(PSR_EUNSUPPORTED, "reactor working set (" + std::to_string(lds) +
                                       " B) exceeds the LDS of one workgroup");
   GroupDev gd;
@@ -533,7 +819,11 @@ static psr_status solve_group(const psr_group &g, const psr_solve_opts *o, void 
   HIP_OK(hipEventCreate(&e1));
   HIP_OK(hipEventRecord(e0, stream));
   int rounds = 0;
-  if (o->scheduler == PSR_PERSISTENT) {
+  if (wplan.NP) {
+    const psr_status st = run_wave(gd, od, wplan, mixed, o->scheduler, states, counters, area, stream,
+                                   o->max_lin * 2 + 8, &rounds);
+    if (st != PSR_OK) return st;
+  } else if (o->scheduler == PSR_PERSISTENT) {
     int dev = 0, ncu = 0, per_cu = 0;
     HIP_OK(hipGetDevice(&dev));
     HIP_OK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));

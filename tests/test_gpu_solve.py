@@ -25,38 +25,43 @@ def _oracle(oracle_mod, mech, cond, x0, energy):
     return xs, st
 
 
+@pytest.mark.parametrize("engine", [1, 2])
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("scheduler", [0, 1])
-def test_isothermal_workload(P, oracle_mod, precision, scheduler):
+def test_isothermal_workload(P, oracle_mod, precision, scheduler, engine):
     from psr_inputs import workload
     mech, cond, x0, energy = workload("isothermal")
     xo, _ = _oracle(oracle_mod, mech, cond, x0, energy)
     x, status, nlin, st = solve_gpu(P.Mechanism(mech), cond, x0, energy, precision=precision,
-                                    scheduler=scheduler)
+                                    scheduler=scheduler, engine=engine)
     assert np.all(status == 0)
     err = rel_err(x, xo, mech["species_elems"].shape[0])
     assert err.max() <= TOL[precision], err
 
 
+@pytest.mark.parametrize("engine", [1, 2])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_energy_workload_sample(P, oracle_mod, precision):
+@pytest.mark.parametrize("scheduler", [0, 1])
+def test_energy_workload_sample(P, oracle_mod, precision, scheduler, engine):
     from psr_inputs import workload
     mech, cond, x0, energy = workload("energy", 200)
     xo, so = _oracle(oracle_mod, mech, cond, x0, energy)
     M = P.Mechanism(mech)
     x, status, nlin, st = solve_gpu(M, cond, x0, energy, precision=precision,
-                                    scheduler=P.PSR_PERSISTENT)
+                                    scheduler=scheduler, engine=engine)
     assert np.all(status == 0)
     err = rel_err(x, xo, M.n_species)
     assert err.max() <= TOL[precision], (np.sort(err)[-5:], np.argsort(err)[-5:])
 
 
-def test_schedulers_agree_bitwise(P):
+@pytest.mark.parametrize("engine", [1, 2])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_schedulers_agree_bitwise(P, engine, precision):
     from psr_inputs import workload
     mech, cond, x0, energy = workload("energy", 96)
     M = P.Mechanism(mech)
-    a = solve_gpu(M, cond, x0, energy, scheduler=P.PSR_PLAIN)
-    b = solve_gpu(M, cond, x0, energy, scheduler=P.PSR_PERSISTENT)
+    a = solve_gpu(M, cond, x0, energy, scheduler=P.PSR_PLAIN, engine=engine, precision=precision)
+    b = solve_gpu(M, cond, x0, energy, scheduler=P.PSR_PERSISTENT, engine=engine, precision=precision)
     np.testing.assert_array_equal(a[0], b[0])
     np.testing.assert_array_equal(a[1], b[1])
     np.testing.assert_array_equal(a[2], b[2])
@@ -96,3 +101,37 @@ def test_warm_start_and_budget(P, oracle_mod):
     assert np.all(status2 == 0) and np.all(nlin2 <= 2)
     x3, status3, nlin3, _ = solve_gpu(M, cond, x0, energy, max_lin=10)
     assert np.all(status3 == 1) and np.all(nlin3 <= 10)
+
+
+@pytest.mark.parametrize("n_react", [1, 3, 5, 67])
+def test_ragged_batches(P, oracle_mod, n_react):
+    """Batch sizes that leave partly filled workgroups (4 reactors per workgroup)."""
+    from psr_inputs import workload
+    mech, cond, x0, energy = workload("energy", n_react)
+    xo, _ = _oracle(oracle_mod, mech, cond, x0, energy)
+    M = P.Mechanism(mech)
+    for sched in (0, 1):
+        x, status, _, _ = solve_gpu(M, cond, x0, energy, scheduler=sched, precision=1)
+        assert np.all(status == 0)
+        assert rel_err(x, xo, M.n_species).max() <= TOL[1]
+
+
+def test_tiny_mechanisms_on_wave_engine(P, oracle_mod):
+    """n = 2 .. 6 unknowns (NP = 16 register rows), isothermal and with energy."""
+    for mech, energy in ((tm.small_network(), False), (tm.small_network(), True),
+                         (tm.association(), False)):
+        n_sp = mech["species_elems"].shape[0]
+        rng = np.random.default_rng(3)
+        B = 9
+        cond = {"P": np.full(B, 101325.0), "tau": np.exp(rng.uniform(np.log(1e-5), 0, B)),
+                "T_in": rng.uniform(300, 900, B) if energy else np.full(B, 1400.0),
+                "Y_in": rng.dirichlet(np.ones(n_sp), B).T.copy()}
+        x0 = np.concatenate([cond["Y_in"], np.full((1, B), 1500.0)]) if energy else cond["Y_in"].copy()
+        xo, so = oracle_mod.solve_batch(mech, cond, x0, energy)
+        M = P.Mechanism(mech)
+        for prec in (0, 1):
+            x, status, _, _ = solve_gpu(M, cond, x0, energy, precision=prec, engine=2,
+                                        scheduler=P.PSR_PERSISTENT)
+            ok = so["status"] == 0
+            np.testing.assert_array_equal(status[ok], 0)
+            assert rel_err(x[:, ok], xo[:, ok], n_sp).max() <= TOL[prec]
