@@ -6,8 +6,10 @@ psr_inputs).  One step = one psr_solve_batch call that solves the whole batch
 from the same initial guess, with inputs already resident in HBM.
 
 Printed JSON line (one): the mixed-precision persistent solver's rate as
-`value`, the plain FP64 host-driven solver on the same inputs beside it, a
-roofline object for the dominant kernel, parity against the oracle on the
+`value`, the plain FP64 host-driven solver and the persistent FP64 solver on
+the same inputs beside it, a roofline object for the dominant kernel (the
+persistent solve kernel), the residual kernel's throughput on a batch of 1e6
+reactors against the FP64 and HBM peaks, parity against the oracle on the
 CPU-baseline sample, and the oracle's own throughput on the host cores.
 """
 from __future__ import annotations
@@ -24,7 +26,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_ALU_TFLOPS = 78.6   # FP64 vector = non-packed FP32 vector: 256 CU x 64 FMA/clk x 2 x 2.4 GHz
+PEAK_HBM_GBS = 8000.0
+EXP_FLOPS = 20.0         # an FP64 exp counted as its ~20 vector instructions
 TOL = {0: 1e-8, 1: 1e-7}
+
+
+def residual_work(N, I, nnz, n):
+    """Algorithmic FP64 flops and HBM bytes of one residual evaluation of one
+    reactor: thermo (~45 N), per reaction two exps plus ~28 flops (rate
+    constant, equilibrium constant, concentration products), two flops per
+    stoichiometric entry for the production rates; bytes: x, Y_in, P, tau,
+    T_in in, F and the scaled residual out."""
+    flops = I * (2 * EXP_FLOPS + 28.0) + 2.0 * nnz + 45.0 * N
+    nbytes = 8.0 * (n + N + 3) + 8.0 * (n + 1)
+    return flops, nbytes
 
 
 def alg_flops(n, N, I):
@@ -35,6 +50,42 @@ def alg_flops(n, N, I):
     return lin, rnd
 
 
+def rate_kernel(P, B, steps=5):
+    """psr_residual over B reactors of the 53/325 mechanism (inputs resident in
+    HBM), timed with HIP events on the launch stream."""
+    import torch
+    from psr_inputs import workload
+    from tests.gpu_util import cond_dev, dev
+    mech, cond, x0, energy = workload("rate", B)
+    M = P.Mechanism(mech)
+    cd = cond_dev(cond)
+    xd = dev(x0)
+    F = torch.empty_like(xd)
+    sc = torch.empty(B, dtype=torch.float64, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    P.residual(M, cd, energy, xd, F, sc)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        P.residual(M, cd, energy, xd, F, sc)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    N, I = mech["species_elems"].shape[0], mech["A"].shape[0]
+    nnz = int(sum(len(set(int(v) for v in list(mech["reac_idx"][k]) + list(mech["prod_idx"][k]) if v >= 0))
+                  for k in range(I)))
+    fl, by = residual_work(N, I, nnz, x0.shape[0])
+    tf = fl * B / (ms / 1e3) / 1e12
+    gbs = by * B / (ms / 1e3) / 1e9
+    ok = bool(torch.isfinite(F).all().item())
+    return {"kernel": "k_wresidual", "reactors": B, "ms_per_launch": ms,
+            "reactor_evals_per_s": B / (ms / 1e3), "flops_per_reactor": fl,
+            "bytes_per_reactor": by, "achieved_tflops": tf, "peak_tflops": PEAK_ALU_TFLOPS,
+            "frac_fp64": tf / PEAK_ALU_TFLOPS, "achieved_gbs": gbs, "peak_gbs": PEAK_HBM_GBS,
+            "frac_hbm": gbs / PEAK_HBM_GBS, "finite": ok}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -43,8 +94,10 @@ def main():
     ap.add_argument("--workload", default="mixed")
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="reactors for the oracle baseline (0: 384 per host core)")
+                    help="reactors for the oracle baseline (0: the whole batch)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rate-reactors", type=int, default=1_000_000,
+                    help="batch size of the residual-kernel measurement (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus must be 1",
@@ -103,13 +156,21 @@ def main():
     x_plain = x.cpu().numpy()
     s_plain = status.cpu().numpy()
 
+    fp64p = P.default_opts(precision=P.PSR_FP64, scheduler=P.PSR_PERSISTENT)
+    ms_fp64p, _, st_fp64p, _ = run(fp64p, args.plain_steps, 0)
+    s_fp64p = status.cpu().numpy()
+
+    rate = None
+    if args.rate_reactors > 0:
+        rate = rate_kernel(P, args.rate_reactors)
+
     # oracle on a bounded sample: CPU baseline and parity reference
     cpu = None
     parity = None
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         cores = min(os.cpu_count() or 1, 16)
-        S = args.cpu_sample or min(B, 384 * cores)
+        S = args.cpu_sample or B
         idx = np.sort(np.random.default_rng(2024).choice(B, S, replace=False))
         t0 = time.perf_counter()
         xo, so = O.solve_batch(mech, cond, x0, energy, idx=idx, processes=cores)
@@ -152,13 +213,17 @@ def main():
         "fp64_plain": {"value": value_plain, "ms_per_step": ms_plain,
                        "converged": conv_plain, "rounds": st_plain.rounds,
                        "speedup_mixed_over_plain": value / value_plain if value_plain else None},
+        "fp64_persistent": {"value": int((s_fp64p == 0).sum()) / (ms_fp64p / 1e3),
+                            "ms_per_step": ms_fp64p, "note": "context: FP32 and FP64 vector "
+                            "arithmetic run at the same rate on this GPU"},
         "solver": {"converged": conv_mixed, "reactors": B, "lin_total": st_mixed.lin_total,
                    "lin_max": st_mixed.lin_max, "jac_total": st_mixed.jac_total,
                    "fp64_fallbacks": st_mixed.fp64_fallbacks, "wall_ms_per_step": wall_mixed * 1e3},
-        "roofline": {"kernel": "k_persistent<mixed>", "bound": "alu", "achieved": achieved,
+        "roofline": {"kernel": "k_wpersist<64,mixed>", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
                      "traffic": None, "kernel_ms": st_mixed.kernel_ms,
                      "alg_flops": flops},
+        "rate_kernel": rate,
         "parity": parity,
         "cpu_baseline": cpu,
     }

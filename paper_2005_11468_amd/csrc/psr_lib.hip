@@ -389,6 +389,33 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
   }
 }
 
+// Residual of a batch (Eqs. 2-3): one wavefront per reactor, kWR
+// wavefronts per workgroup sharing the LDS tables, grid-stride over reactors
+// so the tables are staged once per workgroup.
+constexpr int kWR = 8;
+
+__global__ void __launch_bounds__(kWR * 64) k_wresidual(GroupDev g, double *F, double *scaled) {
+  extern __shared__ double lds[];
+  char *base = reinterpret_cast<char *>(lds);
+  const Tables t = stage_tables(g.m, base, g.m.packed);
+  __syncthreads();
+  const int n = g.m.N + (g.energy ? 1 : 0);
+  const size_t toff = align16(tables_bytes(g.m.N, g.m.I, g.m.nnz));
+  WArea<64> A;
+  A.at_species(reinterpret_cast<double *>(base + toff) + (size_t)wave_id() * WArea<64>::species_doubles());
+  const int lane = lane_id();
+  for (int64_t b = (int64_t)blockIdx.x * kWR + wave_id(); b < g.B; b += (int64_t)gridDim.x * kWR) {
+    WCtx c;
+    make_wctx<64, false>(c, t, g, b);
+    const double x = lane < n ? g.x[(int64_t)lane * g.B + b] : 0.0;
+    Eval ev;
+    double Fl = 0.0;
+    const double sres = w_residual<64>(c, A, x, Fl, ev, scaled != nullptr);
+    if (lane < n) F[(int64_t)lane * g.B + b] = Fl;
+    if (scaled && lane == 0) scaled[b] = sres;
+  }
+}
+
 }  // namespace wk
 
 // ------------------------------------------------------------ host: mechanism
@@ -584,6 +611,25 @@ extern "C" psr_status psr_residual(psr_mech_t m, const psr_conditions *c, const 
   psr_status st = check_cond(m, c);
   if (st != PSR_OK) return st;
   if (!x || !F) return fail(PSR_EINVAL, "null x or F");
+  const int n = m->N + (c->energy ? 1 : 0);
+  if (m->dev.packed && n <= 64) {
+    const size_t lds = wk::align16(psr::wave::tables_bytes(m->N, m->I, m->nnz)) +
+                       (size_t)wk::kWR * psr::wave::WArea<64>::species_doubles() * 8;
+    if (lds <= (size_t)lds_limit_bytes()) {
+      GroupDev g{};
+      g.m = m->dev;
+      g.energy = c->energy ? 1 : 0;
+      g.B = c->n_reactors;
+      g.P = c->P; g.tau = c->tau; g.Tin = c->T_in; g.Yin = c->Y_in;
+      g.x = const_cast<double *>(x);
+      const int64_t blocks = (c->n_reactors + wk::kWR - 1) / wk::kWR;
+      const unsigned grid = (unsigned)(blocks < 2048 ? blocks : 2048);
+      hipLaunchKernelGGL(wk::k_wresidual, dim3(grid), dim3(wk::kWR * 64), lds, (hipStream_t)stream, g, F,
+                         scaled);
+      HIP_OK(hipGetLastError());
+      return PSR_OK;
+    }
+  }
   const size_t lds = layout_bytes(m, c->energy, false);
   if (lds > (size_t)lds_limit_bytes()) return fail(PSR_EUNSUPPORTED, "mechanism too large for LDS");
   hipLaunchKernelGGL(k_residual, dim3((unsigned)c->n_reactors), dim3(kBS), lds, (hipStream_t)stream,

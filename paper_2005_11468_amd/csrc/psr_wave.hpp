@@ -125,6 +125,14 @@ struct WArea {
     Cs = p; p += WS; gs = p; p += WS; hs = p; p += WS; iSW = p; p += WS; rW = p; p += WS;
     cs = p; p += WS; zs = p;
   }
+  // Species scratch only (no Jacobian rows): residual evaluation.
+  static __host__ __device__ int species_doubles() { return 8 * WS; }
+  __device__ void at_species(double *p) {
+    ldj = 0;
+    J = nullptr;
+    Cs = p; p += WS; gs = p; p += WS; hs = p; p += WS; iSW = p; p += WS; rW = p; p += WS;
+    cs = p; p += WS; zs = p;
+  }
 };
 
 // Per-reactor values of the last residual evaluation.

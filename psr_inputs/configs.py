@@ -7,6 +7,7 @@
 | mixed       | 53/325 (same mechanism)      | 16384  | yes    | as energy     | as energy     | as energy (first 4096 identical) |
 | uneven      | 30/200, 100/600, 200/1200    | 65536  | yes    | U[300,800] K  | 1e-6..1 s     | phi U[0.5,2.5] |
 | soot        | 150/900 + 6 moments          | 8192   | yes    | U[300,800] K  | 1e-3..1e-1 s  | phi U[1.5,3] |
+| rate        | 53/325                       | 1e6    | yes    | U[300,800] K  | 1e-5..1e-1 s  | phi U[0.5,2.5] |
 
 Pressure is 1 atm everywhere (the paper's runs are at 1 atm, Sections 5-6).
 """
@@ -35,6 +36,9 @@ WORKLOADS = {
                    tau_range=(1e-5, 1e-1)),
     "mixed": dict(mech="mixed", B=16384, seed=22, energy=True, recipe="phi",
                   tau_range=(1e-5, 1e-1)),
+    # residual-kernel throughput batch (the paper's largest batch size, 1e6)
+    "rate": dict(mech="mixed", B=1_000_000, seed=62, energy=True, recipe="phi",
+                 tau_range=(1e-5, 1e-1)),
 }
 
 
