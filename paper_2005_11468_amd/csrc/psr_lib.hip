@@ -249,6 +249,14 @@ __host__ __device__ inline int plain_stride(int n) {
   return 10 * WS + NP * WS + (MIXED ? n * WArea<NP>::ldj_of(n) : 0);
 }
 
+// LDS of a wave-engine workgroup: mechanism tables, a copy of the solver
+// options (read from LDS where used, so they do not occupy scalar registers
+// for the whole kernel), then the per-wavefront reactor areas.
+__host__ __device__ inline size_t wave_opts_off(int N, int I, int nnz) { return align16(tables_bytes(N, I, nnz)); }
+__host__ __device__ inline size_t wave_area_off(int N, int I, int nnz) {
+  return wave_opts_off(N, I, nnz) + align16(sizeof(Opts));
+}
+
 template <int NP, bool MIXED>
 __device__ inline void make_wctx(WCtx &c, const Tables &t, const GroupDev &g, int64_t b) {
   const int lane = lane_id();
@@ -279,13 +287,16 @@ __device__ inline void write_result_w(const GroupDev &g, const WCtx &c, const WS
 // queue and solves each reactor to completion; the workgroup's wavefronts
 // share the LDS copy of the mechanism tables.
 template <int NP, bool MIXED>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) k_wpersist(GroupDev g, Opts o, RState *states, int *queue) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) k_wpersist(GroupDev g, Opts og, RState *states, int *queue) {
   extern __shared__ double lds[];
   char *base = reinterpret_cast<char *>(lds);
   const Tables t = stage_tables(g.m, base, g.m.packed);
+  Opts *ol = reinterpret_cast<Opts *>(base + wave_opts_off(g.m.N, g.m.I, g.m.nnz));
+  if (threadIdx.x == 0) *ol = og;
   __syncthreads();
+  const Opts &o = *ol;
   const int n = g.m.N + (g.energy ? 1 : 0);
-  const size_t toff = align16(tables_bytes(g.m.N, g.m.I, g.m.nnz));
+  const size_t toff = wave_area_off(g.m.N, g.m.I, g.m.nnz);
   WArea<NP> A;
   A.at(reinterpret_cast<double *>(base + toff) + (size_t)wave_id() * WArea<NP>::doubles(n), n);
   const int lane = lane_id();
@@ -310,8 +321,7 @@ __device__ inline void save_w(const WCtx &c, const WArea<NP> &A, const WState<NP
 #pragma unroll
   for (int q = 0; q < 9; q++) ar[q * WS + lane] = v[q];
   int *ints = reinterpret_cast<int *>(ar + 9 * WS);
-  ints[lane] = r.pos;
-  ints[WS + lane] = r.perm;
+  ints[lane] = r.perm;
   double *fac = ar + 10 * WS;
   if (r.s.phase == PH_NW_TRIAL || r.s.phase == PH_TS2) {  // factors still in use
 #pragma unroll
@@ -331,8 +341,7 @@ __device__ inline void load_w(const WCtx &c, const WArea<NP> &A, WState<NP, MIXE
   r.t = ar[4 * WS + lane]; r.M = ar[5 * WS + lane]; r.rs = ar[6 * WS + lane]; r.cs = ar[7 * WS + lane];
   r.piv = ar[8 * WS + lane];
   const int *ints = reinterpret_cast<const int *>(ar + 9 * WS);
-  r.pos = ints[lane];
-  r.perm = ints[WS + lane];
+  r.perm = ints[lane];
   const double *fac = ar + 10 * WS;
 #pragma unroll
   for (int j = 0; j < NP; j++) r.a[j] = 0.0;
@@ -352,18 +361,21 @@ __device__ inline void load_w(const WCtx &c, const WArea<NP> &A, WState<NP, MIXE
 // each reactor's vectors (and, while a linearisation is in use, its factors)
 // kept in HBM between launches.
 template <int NP, bool MIXED, bool FIRST>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) k_wround(GroupDev g, Opts o, RState *states, double *area,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) k_wround(GroupDev g, Opts og, RState *states, double *area,
                                                 int stride, int rpw, int *active) {
   extern __shared__ double lds[];
   char *base = reinterpret_cast<char *>(lds);
   const Tables t = stage_tables(g.m, base, g.m.packed);
+  Opts *ol = reinterpret_cast<Opts *>(base + wave_opts_off(g.m.N, g.m.I, g.m.nnz));
+  if (threadIdx.x == 0) *ol = og;
   __syncthreads();
+  const Opts &o = *ol;
   const int n = g.m.N + (g.energy ? 1 : 0);
   const int64_t b = (int64_t)blockIdx.x * rpw + wave_id();
   if (b >= g.B) return;
   RState s0 = states[b];
   if (!FIRST && s0.phase == PH_DONE) return;
-  const size_t toff = align16(tables_bytes(g.m.N, g.m.I, g.m.nnz));
+  const size_t toff = wave_area_off(g.m.N, g.m.I, g.m.nnz);
   WArea<NP> A;
   A.at(reinterpret_cast<double *>(base + toff) + (size_t)wave_id() * WArea<NP>::doubles(n), n);
   const int lane = lane_id();
@@ -714,7 +726,7 @@ static WavePlan wave_plan(psr_mech_t m, int energy, bool mixed, int engine) {
   if (engine == 1 || !m->dev.packed) return w;
   const int NP = wave_np(n);
   if (!NP) return w;
-  const size_t tb = wk::align16(psr::wave::tables_bytes(m->N, m->I, m->nnz));
+  const size_t tb = wk::wave_area_off(m->N, m->I, m->nnz);
   size_t per = 0;
   switch (NP) {
     case 16: per = (size_t)psr::wave::WArea<16>::doubles(n) * 8; break;

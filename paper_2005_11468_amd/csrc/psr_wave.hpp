@@ -11,8 +11,9 @@
 //     (one wavefront owns the area, so the order of the adds is fixed);
 //   * the Jacobian is assembled in LDS (row i = equation i), then lane i loads
 //     row i into VGPRs and the LU runs in registers: the pivot column is found
-//     with a wave reduction, the pivot row is broadcast with readlane, rows are
-//     never moved (the pivot order is kept as a permutation).
+//     with a wave reduction, the pivot row is broadcast with readlane, rows do
+//     not move during the elimination; afterwards pivot row k is moved to lane
+//     k once and L, U are scaled to unit diagonals for the solves.
 // Paper: Section 2 (Eqs. 1-3) and Section 3 (Eqs. 4-9, hybrid method).
 #pragma once
 
@@ -498,51 +499,104 @@ __device__ __forceinline__ int lu_regs(T (&a)[NP], int n, int &pos, int &permk, 
   return info;
 }
 
-template <int NP, int KC, typename T, typename VT>
-__device__ __forceinline__ double lu_forward(const VT &c0, const VT &c1, const VT &c2, const VT &c3, int n, int pos,
-                                             int permk, double pinv, double y) {
-  if constexpr (KC < NP / 16) {
-    const VT &ck = chunk<KC>(const_cast<VT &>(c0), const_cast<VT &>(c1), const_cast<VT &>(c2), const_cast<VT &>(c3));
-    const int kend = n < 16 * KC + 16 ? n : 16 * KC + 16;
-    for (int k = 16 * KC; k < kend; k++) {
-      const double yk = bcast(y, bcast(permk, k)) * bcast(pinv, k);
-      if (pos > k && pos < NP) y -= (double)ck[k & 15] * yk;
+// Lane `src`'s value, for every lane (ds_bpermute; no LDS storage is used).
+__device__ __forceinline__ double bperm(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int NP, int Q, typename VD>
+__device__ __forceinline__ void permute_scale(VD &c0, VD &c1, VD &c2, VD &c3, int src, double pinv) {
+  if constexpr (Q < NP / 16) {
+    const int lane = lane_id();
+    VD &cq = chunk<Q>(c0, c1, c2, c3);
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+      const double v = bperm(cq[j], src);
+      const double pj = bcast(pinv, 16 * Q + j);
+      cq[j] = v * ((16 * Q + j) < lane ? pj : pinv);
     }
-    if (kend < 16 * KC + 16) return y;
-    return lu_forward<NP, KC + 1, T>(c0, c1, c2, c3, n, pos, permk, pinv, y);
+    permute_scale<NP, Q + 1>(c0, c1, c2, c3, src, pinv);
+  }
+}
+
+// Turn the register factors of lu_regs into the form the solves use: lane k
+// (k < n) receives pivot row k (moved with ds_bpermute), its L part
+// (columns j < k) is divided by U_jj and its U part by U_kk, so L and U both
+// have unit diagonals; pinv (lane k) = 1 / U_kk.  Rows of lanes >= n stay 0.
+template <int NP, typename T>
+__device__ __forceinline__ void lu_finish(const T (&f)[NP], double (&a)[NP], int n, int permk, T pivk,
+                                          double &pinv) {
+  typedef typename V16<double>::type VD;
+  VD c0, c1, c2, c3;
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    c0[j] = (double)f[j];
+    c1[j] = NP > 16 ? (double)f[(NP > 16 ? 16 : 0) + j] : 0.0;
+    c2[j] = NP > 32 ? (double)f[(NP > 32 ? 32 : 0) + j] : 0.0;
+    c3[j] = NP > 48 ? (double)f[(NP > 48 ? 48 : 0) + j] : 0.0;
+  }
+  const int lane = lane_id();
+  pinv = 1.0 / (double)pivk;
+  permute_scale<NP, 0>(c0, c1, c2, c3, lane < n ? permk : lane, pinv);
+  vec_to_row<NP, double>(c0, c1, c2, c3, a);
+}
+
+// The substitution loops are unrolled (compile-time column index, no
+// relative register moves); a uniform guard stops at column n.
+template <int NP, int KC, typename VD>
+__device__ __forceinline__ double solve_lower(const VD &c0, const VD &c1, const VD &c2, const VD &c3, int n,
+                                              double y) {
+  if constexpr (KC < NP / 16) {
+    const int lane = lane_id();
+    const VD &ck = chunk<KC>(const_cast<VD &>(c0), const_cast<VD &>(c1), const_cast<VD &>(c2), const_cast<VD &>(c3));
+#pragma unroll
+    for (int kk = 0; kk < 16; kk++) {
+      const int k = 16 * KC + kk;
+      if (k >= n) return y;
+      const double l = lane > k ? ck[kk] : 0.0;  // masked operand keeps y off the select
+      y = fma(-l, bcast(y, k), y);
+    }
+    return solve_lower<NP, KC + 1>(c0, c1, c2, c3, n, y);
   }
   return y;
 }
 
-template <int NP, int KC, typename T, typename VT>
-__device__ __forceinline__ void lu_backward(const VT &c0, const VT &c1, const VT &c2, const VT &c3, int n, int pos,
-                                            int permk, double pinv, double &y, double &z) {
+template <int NP, int KC, typename VD>
+__device__ __forceinline__ double solve_upper(const VD &c0, const VD &c1, const VD &c2, const VD &c3, int n,
+                                              double y) {
   if constexpr (KC >= 0) {
-    const VT &ck = chunk<KC>(const_cast<VT &>(c0), const_cast<VT &>(c1), const_cast<VT &>(c2), const_cast<VT &>(c3));
     const int lane = lane_id();
-    const int kend = n < 16 * KC + 16 ? n : 16 * KC + 16;
-    for (int k = kend - 1; k >= 16 * KC; k--) {
-      const double xk = bcast(y, bcast(permk, k)) * bcast(pinv, k);
-      if (pos >= 0 && pos < k) y -= (double)ck[k & 15] * xk;
-      if (lane == k) z = xk;
+    const VD &ck = chunk<KC>(const_cast<VD &>(c0), const_cast<VD &>(c1), const_cast<VD &>(c2), const_cast<VD &>(c3));
+#pragma unroll
+    for (int kk = 15; kk >= 0; kk--) {
+      const int k = 16 * KC + kk;
+      if (k < n) {
+        const double u = lane < k ? ck[kk] : 0.0;
+        y = fma(-u, bcast(y, k), y);
+      }
     }
-    lu_backward<NP, KC - 1, T>(c0, c1, c2, c3, n, pos, permk, pinv, y, z);
+    return solve_upper<NP, KC - 1>(c0, c1, c2, c3, n, y);
   }
+  return y;
 }
 
-// Solve (P L U) z = b with the register factors; b, z: lane i holds element i.
-// Forward: y_r -= (a_rk / U_kk) y_k for the rows pivoted after step k;
-// backward: x_k = y_k / U_kk, y_r -= a_rk x_k for the rows pivoted before k.
-template <int NP, typename T>
-__device__ __forceinline__ double lu_regs_solve(const T (&a)[NP], int n, int pos, int permk, T pivk, double b) {
-  typedef typename V16<T>::type VT;
-  VT c0, c1, c2, c3;
-  row_to_vec<NP, T>(a, c0, c1, c2, c3);
-  const double pinv = 1.0 / (double)pivk;  // lane k: 1 / U_kk
-  double y = lu_forward<NP, 0, T>(c0, c1, c2, c3, n, pos, permk, pinv, b);
-  double z = 0.0;
-  lu_backward<NP, NP / 16 - 1, T>(c0, c1, c2, c3, n, pos, permk, pinv, y, z);
-  return z;
+// Solve (P L U) z = b with the factors of lu_finish; b, z: lane i holds
+// element i.  y = P b (gathered with ds_bpermute), unit-lower forward
+// substitution, scaling by 1 / U_kk, unit-upper back substitution.  Each step
+// is one readlane of the newly final element and one FMA.
+template <int NP>
+__device__ __forceinline__ double lu_solve_w(const double (&a)[NP], int n, int perm, double pinv, double b) {
+  typedef typename V16<double>::type VD;
+  VD c0, c1, c2, c3;
+  row_to_vec<NP, double>(a, c0, c1, c2, c3);
+  const int lane = lane_id();
+  double y = bperm(b, lane < n ? perm : lane);
+  y = solve_lower<NP, 0>(c0, c1, c2, c3, n, y);
+  y *= pinv;
+  return solve_upper<NP, NP / 16 - 1>(c0, c1, c2, c3, n, y);
 }
 
 }  // namespace wave

@@ -13,11 +13,13 @@ namespace wave {
 template <int NP, bool MIXED>
 struct WState {
   double x, xnw, xev, d, t, M, rs, cs;  // lane vectors (lanes >= n hold 0)
-  // LU factors of this linearisation (register LU layout): FP64 factors, or
-  // in mixed mode the FP32 factors of the equilibrated matrix (widened; the
-  // widening is exact) unless the linearisation fell back to FP64 (s.fb64)
+  // LU factors of this linearisation in the form of lu_finish (lane k: pivot
+  // row k, unit L and U, pinv = 1 / U_kk, perm = lane of pivot row k before
+  // the permutation): FP64 factors, or in mixed mode the widened FP32
+  // factors of the equilibrated matrix unless the linearisation fell back to
+  // FP64 (s.fb64)
   double a[NP];
-  int pos, perm;
+  int perm;
   double piv;
   RState s;
 };
@@ -98,7 +100,11 @@ __device__ __forceinline__ void reject_ts_w(const Opts &o, WState<NP, MIXED> &r,
 template <int NP, bool MIXED>
 __device__ __forceinline__ int factor64(const WCtx &c, const WArea<NP> &A, WState<NP, MIXED> &r) {
   load_rows64<NP>(c, A, r.a);
-  return lu_regs<NP, double>(r.a, c.n, r.pos, r.perm, r.piv);
+  int pos;
+  double pk;
+  const int info = lu_regs<NP, double>(r.a, c.n, pos, r.perm, pk);
+  lu_finish<NP, double>(r.a, r.a, c.n, r.perm, pk, r.piv);
+  return info;
 }
 
 // Mixed precision: equilibrate the LDS rows by powers of two (rows, then
@@ -137,10 +143,9 @@ __device__ __forceinline__ int factor32(const WCtx &c, const WArea<NP> &A, WStat
   }
   wsync();
   float pf = 1.0f;
-  const int info = lu_regs<NP, float>(f, n, r.pos, r.perm, pf);
-#pragma unroll
-  for (int j = 0; j < NP; j++) r.a[j] = (double)f[j];
-  r.piv = (double)pf;
+  int pos;
+  const int info = lu_regs<NP, float>(f, n, pos, r.perm, pf);
+  lu_finish<NP, float>(f, r.a, n, r.perm, pf, r.piv);
   return info;
 }
 
@@ -154,36 +159,45 @@ __device__ __forceinline__ double solve_w(const WCtx &c, const WArea<NP> &A, con
                           double b) {
   const int lane = lane_id(), n = c.n;
   const bool in = lane < n;
-  if (!MIXED || r.s.fb64) return lu_regs_solve<NP, double>(r.a, n, r.pos, r.perm, r.piv, b);
-  if constexpr (MIXED) {
-    const double *row = A.J + (in ? lane : 0) * A.ldj;
-    double z = lu_regs_solve<NP, double>(r.a, n, r.pos, r.perm, r.piv, r.rs * b) * r.cs;
-    double prev = __builtin_inf();
-    bool ok = false;
-    for (int it = 0; it < o.max_refine; it++) {
-      A.zs[lane] = in ? z : 0.0;
-      wsync();
-      double acc = b;
-      if (in) {
-#pragma unroll 8
-        for (int j = 0; j < n; j++) acc -= row[j] * A.zs[j];
-      }
-      wsync();
-      const double dz = lu_regs_solve<NP, double>(r.a, n, r.pos, r.perm, r.piv, r.rs * (in ? acc : 0.0)) * r.cs;
-      z += dz;
+  const double *row = A.J + (in ? lane : 0) * A.ldj;
+  // One call site of the (unrolled) substitution: sweep 0 solves for z, the
+  // refinement sweeps for corrections, and after an FP64 fallback the sweep
+  // solves the unscaled system directly.
+  bool fp64 = !MIXED || r.s.fb64;
+  double z = 0.0, acc = b, prev = __builtin_inf();
+  for (int it = 0;; it++) {
+    const double rhs = fp64 ? b : r.rs * (in ? acc : 0.0);
+    const double sol = lu_solve_w<NP>(r.a, n, r.perm, r.piv, rhs);
+    if (fp64) return sol;
+    const double dz = sol * r.cs;
+    z = (it == 0) ? dz : z + dz;
+    bool fallback = false;
+    if (it > 0) {
       const double dn = wmax(in ? fabs(dz) : 0.0), zn = wmax(in ? fabs(z) : 0.0);
-      if (dn <= 1e-10 * zn) { ok = true; break; }
-      if (!(dn <= 0.5 * prev)) break;
+      if (dn <= 1e-10 * zn) return z;
+      fallback = !(dn <= 0.5 * prev) || it >= o.max_refine;
       prev = dn;
+    } else if (o.max_refine <= 0) {
+      fallback = true;
     }
-    if (ok) return z;
-    r.s.fb64 = 1;
-    r.s.n_fb64++;
-    r.s.sing = factor64<NP, MIXED>(c, A, r) != 0;
-    if (r.s.sing) return __builtin_nan("");
-    return lu_regs_solve<NP, double>(r.a, n, r.pos, r.perm, r.piv, b);
+    if (fallback) {
+      r.s.fb64 = 1;
+      r.s.n_fb64++;
+      r.s.sing = factor64<NP, MIXED>(c, A, r) != 0;
+      if (r.s.sing) return __builtin_nan("");
+      fp64 = true;
+      continue;
+    }
+    // FP64 residual of the refined solution against the FP64 matrix in LDS
+    A.zs[lane] = in ? z : 0.0;
+    wsync();
+    acc = b;
+    if (in) {
+#pragma unroll 8
+      for (int j = 0; j < n; j++) acc -= row[j] * A.zs[j];
+    }
+    wsync();
   }
-  return 0.0;
 }
 
 // One round of the controller (see psr_solver.hpp for the phase semantics).
@@ -341,7 +355,7 @@ __device__ __forceinline__ void init_w(const WCtx &c, const Opts &o, WState<NP, 
   r.x = (lane < c.n) ? ((lane < c.N && !(x0 > 0.0)) ? 0.0 : x0) : 0.0;
   r.xnw = r.xev = r.d = r.t = r.M = 0.0;
   r.rs = r.cs = 1.0;
-  r.pos = r.perm = 0;
+  r.perm = 0;
   r.piv = 1.0;
   RState &s = r.s;
   s.phase = PH_NW_BASE;
