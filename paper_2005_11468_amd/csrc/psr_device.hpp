@@ -59,19 +59,24 @@ struct Layout {
   int Yin, Hin;                                       // inlet data
   int x, xnw, xev, d, t, M, G, rs, cs, rb, rr;        // vectors
   int A64, A32, piv, persist;                         // matrices
+  int split, mat_total;  // split: matrices in a separate (HBM) area of mat_total doubles
   int C, hRT, sR, cpR, wdot, gross, Erow, dwdT;       // species scratch
   int kf, kr, Rf, Rr, sumC, dqdT, dqdC;               // reaction scratch
   int red, total;
-  __host__ __device__ void make(int N_, int I_, int n_, bool mixed, int BS) {
+  __host__ __device__ void make(int N_, int I_, int n_, bool mixed, int BS, bool split_ = false) {
     N = N_; I = I_; n = n_;
     lda = (n % 2 == 0) ? n + 1 : n;
+    split = split_ ? 1 : 0;
     int o = 0;
     Yin = o; o += N; Hin = o; o += N;
     x = o; o += n; xnw = o; o += n; xev = o; o += n; d = o; o += n; t = o; o += n;
     M = o; o += n; G = o; o += n; rs = o; o += n; cs = o; o += n; rb = o; o += n; rr = o; o += n;
-    A64 = o; o += n * lda;
-    A32 = o; o += mixed ? (n * lda + 1) / 2 : 0;
-    piv = o; o += (n + 1) / 2;
+    int m = split ? 0 : o;  // matrices follow the vectors, or start their own area
+    A64 = m; m += n * lda;
+    A32 = m; m += mixed ? (n * lda + 1) / 2 : 0;
+    piv = m; m += (n + 1) / 2;
+    if (split) mat_total = m;
+    else { mat_total = 0; o = m; }
     persist = o;
     C = o; o += N; hRT = o; o += N; sR = o; o += N; cpR = o; o += N; wdot = o; o += N;
     gross = o; o += N; Erow = o; o += N; dwdT = o; o += N;
@@ -124,10 +129,14 @@ struct Ctx {
   int N, n, energy;
   double P, tau, Tin;
   double *base;  // start of the reactor's area (doubles)
+  double *mat;   // split layout: start of the reactor's matrix area (HBM), else null
   Layout L;
   // scalars of the last residual evaluation
   double T, S, rho, mdot;
   __device__ double *p(int off) const { return base + off; }
+  __device__ double *A64() const { return (mat ? mat : base) + L.A64; }
+  __device__ float *A32() const { return reinterpret_cast<float *>((mat ? mat : base) + L.A32); }
+  __device__ int *piv() const { return reinterpret_cast<int *>((mat ? mat : base) + L.piv); }
 };
 
 // Set up a reactor: inlet composition and molar inlet enthalpies H_i(T_in).

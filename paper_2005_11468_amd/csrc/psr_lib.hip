@@ -73,6 +73,7 @@ __device__ inline Ctx make_ctx(const MechDev &m, const Layout &L, int energy, do
   c.tau = tau;
   c.Tin = Tin;
   c.base = base;
+  c.mat = nullptr;
   c.L = L;
   return c;
 }
@@ -84,7 +85,7 @@ __global__ void __launch_bounds__(kBS) k_residual(MechDev m, int energy, int64_t
   extern __shared__ double lds[];
   const int64_t b = blockIdx.x;
   Layout L;
-  L.make(m.N, m.I, m.N + (energy ? 1 : 0), false, kBS);
+  L.make(m.N, m.I, m.N + (energy ? 1 : 0), false, kBS, true);  // no matrix needed
   Ctx c = make_ctx(m, L, energy, P[b], tau[b], Tin[b], lds);
   load_inlet<kBS>(c, Yin, B, b);
   double *xl = c.p(L.x), *G = c.p(L.G);
@@ -101,17 +102,15 @@ __global__ void __launch_bounds__(kBS) k_jacobian(MechDev m, int energy, int64_t
   extern __shared__ double lds[];
   const int64_t b = blockIdx.x;
   Layout L;
-  L.make(m.N, m.I, m.N + (energy ? 1 : 0), false, kBS);
+  L.make(m.N, m.I, m.N + (energy ? 1 : 0), false, kBS, true);  // the matrix is the output
   Ctx c = make_ctx(m, L, energy, P[b], tau[b], Tin[b], lds);
   load_inlet<kBS>(c, Yin, B, b);
-  double *xl = c.p(L.x), *G = c.p(L.G), *A = c.p(L.A64);
+  double *xl = c.p(L.x), *G = c.p(L.G);
   const int n = c.n;
   for (int i = threadIdx.x; i < n; i += kBS) xl[i] = x[(int64_t)i * B + b];
   __syncthreads();
   residual<kBS>(c, xl, G, false);
-  jacobian<kBS>(c, xl, A, L.lda);
-  double *out = J + (int64_t)b * n * n;
-  for (int e = threadIdx.x; e < n * n; e += kBS) out[e] = A[(e / n) * L.lda + (e % n)];
+  jacobian<kBS>(c, xl, J + (int64_t)b * n * n, n);
 }
 
 template <typename T>
@@ -172,15 +171,17 @@ __device__ inline void write_result(const GroupDev &g, const Ctx &c, const RStat
 // reactor's area lives in HBM (`area`, [B][persist]) between launches.
 template <bool MIXED, bool FIRST>
 __global__ void __launch_bounds__(kBS) k_round(GroupDev g, Opts o, RState *states, double *area,
-                                               int persist, int *active) {
+                                               int split, int *active) {
   extern __shared__ double lds[];
   const int64_t b = blockIdx.x;
   RState s = states[b];
   if (!FIRST && s.phase == PH_DONE) return;
   Layout L;
-  L.make(g.m.N, g.m.I, g.m.N + (g.energy ? 1 : 0), MIXED, kBS);
+  L.make(g.m.N, g.m.I, g.m.N + (g.energy ? 1 : 0), MIXED, kBS, split != 0);
   Ctx c = make_ctx(g.m, L, g.energy, g.P[b], g.tau[b], g.Tin[b], lds);
-  double *mine = area + b * (int64_t)persist;
+  const int persist = L.persist;
+  double *mine = area + b * (int64_t)(L.persist + L.mat_total);
+  if (split) c.mat = mine + L.persist;  // the matrices stay in HBM
   if (FIRST) {
     load_inlet<kBS>(c, g.Yin, g.B, b);
     double *xl = c.p(L.x);
@@ -205,10 +206,11 @@ __global__ void __launch_bounds__(kBS) k_round(GroupDev g, Opts o, RState *state
 // workgroup takes the next reactor index from `queue` until none is left,
 // and runs it to completion with every array in LDS.
 template <bool MIXED>
-__global__ void __launch_bounds__(kBS) k_persistent(GroupDev g, Opts o, RState *states, int *queue) {
+__global__ void __launch_bounds__(kBS) k_persistent(GroupDev g, Opts o, RState *states, int *queue,
+                                                    double *matws) {
   extern __shared__ double lds[];
   Layout L;
-  L.make(g.m.N, g.m.I, g.m.N + (g.energy ? 1 : 0), MIXED, kBS);
+  L.make(g.m.N, g.m.I, g.m.N + (g.energy ? 1 : 0), MIXED, kBS, matws != nullptr);
   int *next = reinterpret_cast<int *>(lds + L.red + kBS + 4);
   for (;;) {
     if (threadIdx.x == 0) *next = atomicAdd(queue, 1);
@@ -217,6 +219,7 @@ __global__ void __launch_bounds__(kBS) k_persistent(GroupDev g, Opts o, RState *
     __syncthreads();
     if (b >= g.B) break;
     Ctx c = make_ctx(g.m, L, g.energy, g.P[b], g.tau[b], g.Tin[b], lds);
+    if (matws) c.mat = matws + (int64_t)blockIdx.x * L.mat_total;  // this workgroup's HBM matrices
     load_inlet<kBS>(c, g.Yin, g.B, b);
     double *xl = c.p(L.x);
     for (int i = threadIdx.x; i < c.n; i += kBS) xl[i] = g.x[(int64_t)i * g.B + b];
@@ -612,10 +615,33 @@ static psr_status check_cond(psr_mech_t m, const psr_conditions *c) {
   return PSR_OK;
 }
 
-static size_t layout_bytes(psr_mech_t m, int energy, bool mixed) {
+static size_t layout_bytes(psr_mech_t m, int energy, bool mixed, bool split = false) {
   Layout L;
-  L.make(m->N, m->I, m->N + (energy ? 1 : 0), mixed, kBS);
+  L.make(m->N, m->I, m->N + (energy ? 1 : 0), mixed, kBS, split);
   return (size_t)L.total * 8;
+}
+
+// Block-engine layout of a group: everything in LDS when it fits, else the
+// matrices in HBM (split).  Returns false if even the split layout exceeds
+// the LDS of one workgroup.
+static bool block_layout(psr_mech_t m, int energy, bool mixed, Layout &L) {
+  L.make(m->N, m->I, m->N + (energy ? 1 : 0), mixed, kBS, false);
+  if ((size_t)L.total * 8 <= (size_t)lds_limit_bytes()) return true;
+  L.make(m->N, m->I, m->N + (energy ? 1 : 0), mixed, kBS, true);
+  return (size_t)L.total * 8 <= (size_t)lds_limit_bytes();
+}
+
+// Resident workgroups of the block engine's persistent kernel.
+static int64_t block_grid(const Layout &L, bool mixed, int64_t B) {
+  int dev = 0, ncu = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  const size_t lds = (size_t)L.total * 8;
+  hipError_t e = mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<true>, kBS, lds)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<false>, kBS, lds);
+  if (e != hipSuccess) return 0;
+  if (per_cu < 1) per_cu = 1;
+  return std::min<int64_t>(B, (int64_t)ncu * per_cu);
 }
 
 extern "C" psr_status psr_residual(psr_mech_t m, const psr_conditions *c, const double *x, double *F,
@@ -642,7 +668,7 @@ extern "C" psr_status psr_residual(psr_mech_t m, const psr_conditions *c, const 
       return PSR_OK;
     }
   }
-  const size_t lds = layout_bytes(m, c->energy, false);
+  const size_t lds = layout_bytes(m, c->energy, false, true);
   if (lds > (size_t)lds_limit_bytes()) return fail(PSR_EUNSUPPORTED, "mechanism too large for LDS");
   hipLaunchKernelGGL(k_residual, dim3((unsigned)c->n_reactors), dim3(kBS), lds, (hipStream_t)stream,
                      m->dev, c->energy ? 1 : 0, c->n_reactors, c->P, c->tau, c->T_in, c->Y_in, x, F,
@@ -656,7 +682,7 @@ extern "C" psr_status psr_jacobian(psr_mech_t m, const psr_conditions *c, const 
   psr_status st = check_cond(m, c);
   if (st != PSR_OK) return st;
   if (!x || !J) return fail(PSR_EINVAL, "null x or J");
-  const size_t lds = layout_bytes(m, c->energy, false);
+  const size_t lds = layout_bytes(m, c->energy, false, true);
   if (lds > (size_t)lds_limit_bytes()) return fail(PSR_EUNSUPPORTED, "mechanism too large for LDS");
   hipLaunchKernelGGL(k_jacobian, dim3((unsigned)c->n_reactors), dim3(kBS), lds, (hipStream_t)stream,
                      m->dev, c->energy ? 1 : 0, c->n_reactors, c->P, c->tau, c->T_in, c->Y_in, x, J);
@@ -815,11 +841,13 @@ static psr_status run_wave(const GroupDev &gd, const Opts &od, const WavePlan &w
 static size_t group_ws(const psr_group &g, const psr_solve_opts *o) {
   Layout L;
   const bool mixed = o->precision == PSR_MIXED;
-  L.make(g.mech->N, g.mech->I, g.mech->N + (g.cond.energy ? 1 : 0), mixed, kBS);
+  block_layout(g.mech, g.cond.energy, mixed, L);
   size_t bytes = align256(sizeof(RState) * (size_t)g.cond.n_reactors) + 256;
   const WavePlan w = wave_plan(g.mech, g.cond.energy, mixed, o->engine);
   if (o->scheduler == PSR_PLAIN)
-    bytes += align256((size_t)(w.NP ? w.stride : L.persist) * 8 * g.cond.n_reactors);
+    bytes += align256((size_t)(w.NP ? w.stride : L.persist + L.mat_total) * 8 * g.cond.n_reactors);
+  else if (!w.NP && L.split)
+    bytes += align256((size_t)L.mat_total * 8 * block_grid(L, mixed, g.cond.n_reactors));
   return bytes;
 }
 
@@ -852,14 +880,14 @@ static psr_status solve_group(const psr_group &g, const psr_solve_opts *o, void 
   const bool mixed = o->precision == PSR_MIXED;
   const int64_t B = g.cond.n_reactors;
   Layout L;
-  L.make(g.mech->N, g.mech->I, g.mech->N + (g.cond.energy ? 1 : 0), mixed, kBS);
+  const bool fits = block_layout(g.mech, g.cond.energy, mixed, L);
   const size_t lds = (size_t)L.total * 8;
   const WavePlan wplan = wave_plan(g.mech, g.cond.energy, mixed, o->engine);
   if (o->engine == 2 && !wplan.NP)
     return fail(PSR_EUNSUPPORTED, "wavefront engine needs n <= 64 and a mechanism that fits its LDS");
-  if (!wplan.NP && lds > (size_t)lds_limit_bytes())
+  if (!wplan.NP && !fits)
     return fail(PSR_EUNSUPPORTED, "reactor working set (" + std::to_string(lds) +
-                                      " B) exceeds the LDS of one workgroup");
+                                      " B without matrices) exceeds the LDS of one workgroup");
   GroupDev gd;
   gd.m = g.mech->dev; gd.energy = g.cond.energy ? 1 : 0; gd.B = B;
   gd.P = g.cond.P; gd.tau = g.cond.tau; gd.Tin = g.cond.T_in; gd.Yin = g.cond.Y_in;
@@ -882,31 +910,25 @@ static psr_status solve_group(const psr_group &g, const psr_solve_opts *o, void 
                                    o->max_lin * 2 + 8, &rounds);
     if (st != PSR_OK) return st;
   } else if (o->scheduler == PSR_PERSISTENT) {
-    int dev = 0, ncu = 0, per_cu = 0;
-    HIP_OK(hipGetDevice(&dev));
-    HIP_OK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    if (mixed)
-      HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<true>, kBS, lds));
-    else
-      HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<false>, kBS, lds));
-    if (per_cu < 1) per_cu = 1;
-    const int64_t grid = std::min<int64_t>(B, (int64_t)ncu * per_cu);
+    const int64_t grid = block_grid(L, mixed, B);
+    if (grid <= 0) return fail(PSR_EDEVICE, "occupancy query failed");
+    double *matws = L.split ? area : nullptr;  // one HBM matrix area per resident workgroup
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, counters, 64);
     if (mixed)
       hipLaunchKernelGGL(k_persistent<true>, dim3((unsigned)grid), dim3(kBS), lds, stream, gd, od, states,
-                         counters);
+                         counters, matws);
     else
       hipLaunchKernelGGL(k_persistent<false>, dim3((unsigned)grid), dim3(kBS), lds, stream, gd, od, states,
-                         counters);
+                         counters, matws);
     HIP_OK(hipGetLastError());
   } else {
     const int check_every = 4;
     if (mixed)
       hipLaunchKernelGGL((k_round<true, true>), dim3((unsigned)B), dim3(kBS), lds, stream, gd, od, states,
-                         area, L.persist, counters);
+                         area, L.split, counters);
     else
       hipLaunchKernelGGL((k_round<false, true>), dim3((unsigned)B), dim3(kBS), lds, stream, gd, od, states,
-                         area, L.persist, counters);
+                         area, L.split, counters);
     HIP_OK(hipGetLastError());
     int active = 1;
     const int max_rounds = o->max_lin * 2 + 8;
@@ -915,10 +937,10 @@ static psr_status solve_group(const psr_group &g, const psr_solve_opts *o, void 
       for (int r = 0; r < check_every; r++) {
         if (mixed)
           hipLaunchKernelGGL((k_round<true, false>), dim3((unsigned)B), dim3(kBS), lds, stream, gd, od,
-                             states, area, L.persist, counters);
+                             states, area, L.split, counters);
         else
           hipLaunchKernelGGL((k_round<false, false>), dim3((unsigned)B), dim3(kBS), lds, stream, gd, od,
-                             states, area, L.persist, counters);
+                             states, area, L.split, counters);
         rounds++;
       }
       HIP_OK(hipGetLastError());

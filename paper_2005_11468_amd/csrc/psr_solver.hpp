@@ -122,14 +122,14 @@ template <int BS, bool MIXED>
 __device__ void solve_round(const Ctx &c, const Opts &o, RState &s, const double *b, double *z) {
   const int n = c.n, lda = c.L.lda;
   double *red = c.p(c.L.red);
-  double *A64 = c.p(c.L.A64);
-  int *piv = reinterpret_cast<int *>(c.p(c.L.piv));
+  double *A64 = c.A64();
+  int *piv = c.piv();
   if (!MIXED || s.fb64) {
     vcopy<BS>(z, b, n);
     lu_solve<BS, double>(A64, n, lda, piv, z);
     return;
   }
-  const float *A32 = reinterpret_cast<const float *>(c.p(c.L.A32));
+  const float *A32 = c.A32();
   const double *rs = c.p(c.L.rs), *cs = c.p(c.L.cs);
   double *r = c.p(c.L.rr), *bb = c.p(c.L.rb);
   vcopy<BS>(bb, b, n);
@@ -221,8 +221,8 @@ __device__ void round_step(Ctx &c, const Opts &o, RState &s) {
   const int n = c.n, N = c.N, lda = L.lda;
   double *red = c.p(L.red);
   double *x = c.p(L.x), *xnw = c.p(L.xnw), *xev = c.p(L.xev), *d = c.p(L.d), *t = c.p(L.t);
-  double *M = c.p(L.M), *G = c.p(L.G), *A64 = c.p(L.A64);
-  int *piv = reinterpret_cast<int *>(c.p(L.piv));
+  double *M = c.p(L.M), *G = c.p(L.G), *A64 = c.A64();
+  int *piv = c.piv();
   const int ph = s.phase;
   const bool lin = (ph == PH_NW_BASE || ph == PH_TS1);
 
@@ -240,7 +240,7 @@ __device__ void round_step(Ctx &c, const Opts &o, RState &s) {
     s.sing = 0;
     if (s.fin) {
       if (MIXED) {
-        const int info = factor_mixed<BS>(c, A64, reinterpret_cast<float *>(c.p(L.A32)), piv,
+        const int info = factor_mixed<BS>(c, A64, c.A32(), piv,
                                           c.p(L.rs), c.p(L.cs), red);
         if (info != 0) {
           s.fb64 = 1;

@@ -90,7 +90,7 @@ def _species_list(rng, n_species, soot):
     return np.array(comps, dtype=np.int32)
 
 
-def _nasa7(rng, comps, roles):
+def _nasa7(rng, comps, roles, heat_scale=1.0):
     """Single-range NASA-7 coefficients a1..a7 per species.
 
     c_p/R = a1 + a2 T + a3 T^2 + a4 T^3 + a5 T^4 is positive on [300, 3000] K by
@@ -108,9 +108,9 @@ def _nasa7(rng, comps, roles):
     a[:, 4] = poly * rng.uniform(0.0, 1.0e-16, n)
     h = -BOND_ENTHALPY * poly + rng.uniform(-NOISE_ENTHALPY, NOISE_ENTHALPY, n)
     for i in roles.get("fuel_ox", []):
-        h[i] += FUEL_OX_OFFSET
+        h[i] += heat_scale * FUEL_OX_OFFSET
     for i in roles.get("products", []):
-        h[i] += PRODUCT_OFFSET
+        h[i] += heat_scale * PRODUCT_OFFSET
     a[:, 5] = h / R_GAS
     s_target = S_PER_MOLECULE + S_PER_ATOM * na + rng.uniform(-2.0, 2.0, n)
     a[:, 6] = s_target - a[:, 0] * LN_T_REF
@@ -139,7 +139,8 @@ def _multiset_table(n_reactive, comps, size):
     return ms[order].astype(np.int32), key[order]
 
 
-def make_mechanism(n_species: int, n_reactions: int, seed: int, *, soot: bool = False) -> dict:
+def make_mechanism(n_species: int, n_reactions: int, seed: int, *, soot: bool = False,
+                   heat_scale: float = 1.0) -> dict:
     """Draw an element-balanced reversible mechanism.
 
     Returns a dict of numpy arrays (see module docstring).  Reactant and
@@ -155,7 +156,7 @@ def make_mechanism(n_species: int, n_reactions: int, seed: int, *, soot: bool = 
     oxid = 1
     products = [2, 3]
     roles = {"fuel_ox": [fuel, oxid], "products": products}
-    nasa, h_offset = _nasa7(rng, comps, roles)
+    nasa, h_offset = _nasa7(rng, comps, roles, heat_scale)
 
     tables = {s: _multiset_table(n_reactive, comps, s) for s in (1, 2, 3)}
     p_count = np.array([0.2, 0.6, 0.2])
