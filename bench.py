@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_ALU_TFLOPS = 78.6   # FP64 vector = non-packed FP32 vector: 256 CU x 64 FMA/clk x 2 x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
+PEAK_MFMA_F32_TFLOPS = 157.3
 EXP_FLOPS = 20.0         # an FP64 exp counted as its ~20 vector instructions
 TOL = {0: 1e-8, 1: 1e-7}
 
@@ -86,6 +87,44 @@ def rate_kernel(P, B, steps=5):
             "frac_hbm": gbs / PEAK_HBM_GBS, "finite": ok}
 
 
+def lu_large(P, n=201, B=9830, steps=3):
+    """psr_lu_factor_batch with float factors on B seeded random n x n
+    matrices (the 200/1200 mechanism's matrix size and reactor count of the
+    uneven workload): blocked LU with matrix-core trailing updates; each
+    timed launch factors a fresh copy (the copy is outside the events)."""
+    import torch
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(2011)
+    A0 = torch.randn((B, n, n), dtype=torch.float64, device="cuda:0", generator=g)
+    A = torch.empty_like(A0)
+    piv = torch.empty((B, n), dtype=torch.int32, device="cuda:0")
+    info = torch.empty((B,), dtype=torch.int32, device="cuda:0")
+    import ctypes as C
+    from paper_2005_11468_amd import _lib
+    L = _lib.load()
+    stream = torch.cuda.current_stream()
+    total = 0.0
+    for it in range(steps + 1):
+        A.copy_(A0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        _lib.check(L.psr_lu_factor_batch(n, B, P.PSR_MIXED, C.c_void_p(A.data_ptr()), C.c_void_p(piv.data_ptr()),
+                                         C.c_void_p(info.data_ptr()), C.c_void_p(stream.cuda_stream)),
+                   "psr_lu_factor_batch")
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if it > 0:
+            total += e0.elapsed_time(e1)
+    ms = total / steps
+    flops = 2.0 / 3.0 * n ** 3 * B
+    tf = flops / (ms / 1e3) / 1e12
+    ok = int((info == 0).sum().item())
+    del A0, A
+    return {"kernel": "k_lu_factor_big", "n": n, "matrices": B, "ms_per_launch": ms,
+            "alg_flops": flops, "achieved_tflops": tf, "peak_tflops": PEAK_MFMA_F32_TFLOPS,
+            "frac_mfma_f32": tf / PEAK_MFMA_F32_TFLOPS, "nonsingular": ok}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +135,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="reactors for the oracle baseline (0: the whole batch)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-lu-large", action="store_true")
     ap.add_argument("--rate-reactors", type=int, default=1_000_000,
                     help="batch size of the residual-kernel measurement (0: skip)")
     args = ap.parse_args()
@@ -163,6 +203,7 @@ def main():
     rate = None
     if args.rate_reactors > 0:
         rate = rate_kernel(P, args.rate_reactors)
+    lu_big = lu_large(P) if not args.no_lu_large else None
 
     # oracle on a bounded sample: CPU baseline and parity reference
     cpu = None
@@ -224,6 +265,7 @@ def main():
                      "traffic": None, "kernel_ms": st_mixed.kernel_ms,
                      "alg_flops": flops},
         "rate_kernel": rate,
+        "lu_large": lu_big,
         "parity": parity,
         "cpu_baseline": cpu,
     }

@@ -451,6 +451,158 @@ __device__ int lu_factor(T *A, int n, int lda, int *piv, double *red) {
 }
 
 // Solve (P L U) z = b in place (b in double; factors of type T).
+// Blocked right-looking LU with partial pivoting of a float matrix with up
+// to 256 rows (kept in HBM for the large mechanisms), panel width 16.
+//   panel:    the n - k0 by 16 panel is copied to LDS (pan, row stride 17);
+//             per column a block argmax (first maximum), a row interchange
+//             inside the panel and a rank-one update of the panel rows below;
+//   swaps:    the panel's row interchanges applied to the other columns
+//             (one column per thread);
+//   U12:      L11^-1 A12 by forward substitution, one column per thread, L11
+//             read from the panel in LDS;
+//   A22:      A22 -= L21 U12 on the matrix cores, v_mfma_f32_16x16x4f32 per
+//             16 x 16 tile and K step of 4; each wavefront takes every fourth
+//             tile row and sweeps its tile columns eight at a time.
+// Operand layouts of the 16x16x4 instruction (lane l): A(l % 16, l / 16),
+// B(l / 16, l % 16), D[v](4 (l / 16) + v, l % 16).  Same factor format as
+// lu_factor (unit-lower L below the diagonal, LAPACK pivots).  BS must be
+// 256.  red: LDS scratch of at least 24 doubles; pan: LDS scratch of at
+// least 17 n floats.  Returns 0 or k+1.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <int BS>
+__device__ __forceinline__ int lu_factor_mfma32(float *A, int n, int lda, int *piv, double *red, float *pan) {
+  static_assert(BS == 256, "one panel row per thread");
+  constexpr int PS = 17;  // panel row stride (floats)
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double *wval = red + 16;                        // per-wavefront best |a|
+  int *widx = reinterpret_cast<int *>(red + 20);  // per-wavefront best row
+  for (int k0 = 0; k0 < n; k0 += 16) {
+    const int kb = n - k0 < 16 ? n - k0 : 16;
+    const int rows = n - k0;
+    for (int e = tid; e < rows * 16; e += BS) {
+      const int t = e >> 4, j = e & 15;
+      pan[t * PS + j] = j < kb ? A[(int64_t)(k0 + t) * lda + k0 + j] : 0.f;
+    }
+    __syncthreads();
+    for (int jj = 0; jj < kb; jj++) {
+      const int k = k0 + jj;
+      double v = (tid < rows && tid >= jj) ? fabs((double)pan[tid * PS + jj]) : -1.0;
+      int vi = tid;
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(v, off);
+        const int oi = __shfl_xor(vi, off);
+        if (ov > v || (ov == v && oi < vi)) { v = ov; vi = oi; }
+      }
+      if (lane == 0) { wval[wv] = v; widx[wv] = vi; }
+      __syncthreads();
+      double best = wval[0];
+      int bi = widx[0];
+      for (int w = 1; w < BS / 64; w++)
+        if (wval[w] > best || (wval[w] == best && widx[w] < bi)) { best = wval[w]; bi = widx[w]; }
+      if (!(best > 0.0)) {
+        __syncthreads();
+        return k + 1;
+      }
+      if (tid == 0) piv[k] = k0 + bi;
+      if (bi != jj && tid < 16) {
+        const float t = pan[jj * PS + tid];
+        pan[jj * PS + tid] = pan[bi * PS + tid];
+        pan[bi * PS + tid] = t;
+      }
+      __syncthreads();
+      if (tid < rows && tid > jj) {
+        const float l = pan[tid * PS + jj] / pan[jj * PS + jj];
+        pan[tid * PS + jj] = l;
+        for (int j = jj + 1; j < kb; j++) pan[tid * PS + j] -= l * pan[jj * PS + j];
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < rows * 16; e += BS) {
+      const int t = e >> 4, j = e & 15;
+      if (j < kb) A[(int64_t)(k0 + t) * lda + k0 + j] = pan[t * PS + j];
+    }
+    // the panel's interchanges on the other columns, in order
+    for (int c = tid; c < n; c += BS) {
+      if (c >= k0 && c < k0 + kb) continue;
+      for (int jj = 0; jj < kb; jj++) {
+        const int pr = piv[k0 + jj];
+        if (pr != k0 + jj) {
+          float *x = A + (int64_t)(k0 + jj) * lda + c, *y = A + (int64_t)pr * lda + c;
+          const float t = *x;
+          *x = *y;
+          *y = t;
+        }
+      }
+    }
+    __syncthreads();
+    const int R0 = k0 + kb, m = n - R0;
+    if (m <= 0) break;
+    // U12 = L11^-1 A12
+    for (int c = R0 + tid; c < n; c += BS) {
+      float u[16];
+#pragma unroll
+      for (int i = 0; i < 16; i++) u[i] = i < kb ? A[(int64_t)(k0 + i) * lda + c] : 0.f;
+#pragma unroll
+      for (int i = 1; i < 16; i++) {
+        float acc = u[i];
+#pragma unroll
+        for (int q = 0; q < 16; q++)
+          if (q < i) acc -= (i < kb ? pan[i * PS + q] : 0.f) * u[q];
+        u[i] = acc;
+      }
+#pragma unroll
+      for (int i = 0; i < 16; i++)
+        if (i < kb) A[(int64_t)(k0 + i) * lda + c] = u[i];
+    }
+    __syncthreads();
+    // A22 -= L21 U12 on the matrix cores, eight tile columns at a time
+    const int nt = (m + 15) / 16;
+    const int lr = lane & 15, lk = lane >> 4;
+    for (int ti = wv; ti < nt; ti += BS / 64) {
+      float aq[4];
+      const int arow = R0 + 16 * ti + lr;
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const int k = 4 * q + lk;
+        aq[q] = (arow < n && k < kb) ? -A[(int64_t)arow * lda + k0 + k] : 0.f;
+      }
+      const int crow = R0 + 16 * ti + 4 * lk;
+      for (int tj0 = 0; tj0 < nt; tj0 += 8) {
+        float bq[8][4];
+        v4f acc[8];
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+          const int col = R0 + 16 * (tj0 + t) + lr;
+          const bool cin = (tj0 + t) < nt && col < n;
+#pragma unroll
+          for (int q = 0; q < 4; q++) {
+            const int k = 4 * q + lk;
+            bq[t][q] = (cin && k < kb) ? A[(int64_t)(k0 + k) * lda + col] : 0.f;
+          }
+#pragma unroll
+          for (int v = 0; v < 4; v++) acc[t][v] = (cin && crow + v < n) ? A[(int64_t)(crow + v) * lda + col] : 0.f;
+        }
+#pragma unroll
+        for (int t = 0; t < 8; t++)
+#pragma unroll
+          for (int q = 0; q < 4; q++) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(aq[q], bq[t][q], acc[t], 0, 0, 0);
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+          const int col = R0 + 16 * (tj0 + t) + lr;
+          if ((tj0 + t) < nt && col < n) {
+#pragma unroll
+            for (int v = 0; v < 4; v++)
+              if (crow + v < n) A[(int64_t)(crow + v) * lda + col] = acc[t][v];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  return 0;
+}
+
 template <int BS, typename T>
 __device__ void lu_solve(const T *A, int n, int lda, const int *piv, double *b) {
   const int tid = threadIdx.x;

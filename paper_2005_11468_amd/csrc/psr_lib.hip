@@ -130,6 +130,29 @@ __global__ void __launch_bounds__(kBS) k_lu_factor(int n, double *A, int *piv, i
   if (threadIdx.x == 0) info[b] = r;
 }
 
+// Float factors of large matrices (64 < n <= 256): grid-stride over the
+// batch, each workgroup factoring in its own float scratch area in HBM with
+// the blocked matrix-core LU.
+__global__ void __launch_bounds__(kBS) k_lu_factor_big(int n, int64_t batch, double *A, int *piv, int *info,
+                                                       float *scratch) {
+  __shared__ double red[kBS + 8];
+  __shared__ float pan[256 * 17];
+  const int lda = n;
+  float *M = scratch + (int64_t)blockIdx.x * n * n;
+  for (int64_t b = blockIdx.x; b < batch; b += gridDim.x) {
+    double *g = A + b * (int64_t)n * n;
+    for (int e = threadIdx.x; e < n * n; e += kBS) M[e] = (float)g[e];
+    __syncthreads();
+    const int r = lu_factor_mfma32<kBS>(M, n, lda, piv + b * n, red, pan);
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * n; e += kBS) g[e] = (double)M[e];
+    if (r != 0)
+      for (int k = r - 1 + threadIdx.x; k < n; k += kBS) piv[b * n + k] = k;
+    if (threadIdx.x == 0) info[b] = r;
+    __syncthreads();
+  }
+}
+
 __global__ void __launch_bounds__(kBS) k_lu_solve(int n, const double *A, const int *piv, double *rhs) {
   extern __shared__ double lds[];
   const int64_t b = blockIdx.x;
@@ -690,12 +713,44 @@ extern "C" psr_status psr_jacobian(psr_mech_t m, const psr_conditions *c, const 
   return PSR_OK;
 }
 
+// Device scratch of the large-matrix LU entry point, grown on demand and kept
+// for the life of the process (one buffer per device, calls on a device are
+// serialised by the caller's stream use).
+static psr_status lu_scratch(int dev, size_t bytes, float **out) {
+  static std::vector<std::pair<float *, size_t>> bufs;
+  if ((int)bufs.size() <= dev) bufs.resize(dev + 1, {nullptr, 0});
+  auto &b = bufs[dev];
+  if (b.second < bytes) {
+    if (b.first) HIP_OK(hipFree(b.first));
+    b = {nullptr, 0};
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return fail(PSR_ENOMEM, "LU scratch allocation failed");
+    b = {reinterpret_cast<float *>(p), bytes};
+  }
+  *out = b.first;
+  return PSR_OK;
+}
+
 extern "C" psr_status psr_lu_factor_batch(int32_t n, int64_t batch, int32_t precision, double *A,
                                           int32_t *piv, int32_t *info, void *stream) {
   if (n <= 0 || batch <= 0 || !A || !piv || !info) return fail(PSR_EINVAL, "bad LU arguments");
   if (batch > 0x7fffffffLL) return fail(PSR_EUNSUPPORTED, "batch above 2^31-1");
   const int lda = (n % 2 == 0) ? n + 1 : n;
   const bool f32 = precision == PSR_MIXED;
+  if (f32 && n > 64 && n <= 256) {
+    // blocked matrix-core LU, one float scratch matrix per resident workgroup
+    int dev = 0, ncu = 0;
+    HIP_OK(hipGetDevice(&dev));
+    HIP_OK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int64_t grid = std::min<int64_t>(batch, (int64_t)ncu * 2);
+    float *scratch = nullptr;
+    const psr_status st = lu_scratch(dev, (size_t)grid * n * n * sizeof(float), &scratch);
+    if (st != PSR_OK) return st;
+    hipLaunchKernelGGL(k_lu_factor_big, dim3((unsigned)grid), dim3(kBS), 0, (hipStream_t)stream, n, batch, A,
+                       piv, info, scratch);
+    HIP_OK(hipGetLastError());
+    return PSR_OK;
+  }
   const size_t lds = ((size_t)n * lda * (f32 ? 4 : 8) + 7) / 8 * 8 + (kBS + 8) * 8 + (size_t)n * 4 + 8;
   if (lds > (size_t)lds_limit_bytes()) return fail(PSR_EUNSUPPORTED, "matrix too large for LDS");
   if (f32)

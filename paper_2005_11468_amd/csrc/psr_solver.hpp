@@ -97,6 +97,10 @@ __device__ int factor_mixed(const Ctx &c, const double *A64, float *A32, int *pi
     A32[(int64_t)i * lda + j] = (float)(A64[(int64_t)i * lda + j] * rs[i] * cs[j]);
   }
   __syncthreads();
+  // large matrices: blocked matrix-core LU; its panel borrows the reaction
+  // scratch in LDS (not in use between the Jacobian and the next residual)
+  if (BS == 256 && n > 64 && n <= 256 && 12 * c.L.I * 2 >= 17 * n)
+    return lu_factor_mfma32<256>(A32, n, lda, piv, red, reinterpret_cast<float *>(c.p(c.L.kf)));
   return lu_factor<BS, float>(A32, n, lda, piv, red);
 }
 
