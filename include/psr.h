@@ -175,8 +175,12 @@ size_t psr_workspace_bytes(const psr_group *groups, int32_t n_groups, const psr_
 
 /* Solve every reactor of every group.  workspace: device buffer of at
  * least psr_workspace_bytes() bytes (else PSR_ENOMEM).  Blocks until the
- * solve is complete on `stream`.  A reactor that does not converge is not an
- * API error: its status says why.  stats (host, optional) receives totals. */
+ * solve is complete on `stream`.  With the persistent scheduler and several
+ * groups, each group runs in its own workspace region on its own library
+ * stream (default priority, ordered after `stream` and joined back into it),
+ * so the groups' launches overlap; otherwise groups run in turn.  A reactor
+ * that does not converge is not an API error: its status says why.  stats
+ * (host, optional) receives totals; kernel_ms spans the whole call. */
 psr_status psr_solve_batch(const psr_group *groups, int32_t n_groups, const psr_solve_opts *opts,
                            void *workspace, size_t workspace_bytes, psr_solve_stats *stats,
                            void *stream);

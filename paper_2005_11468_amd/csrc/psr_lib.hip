@@ -891,6 +891,12 @@ static psr_status run_wave(const GroupDev &gd, const Opts &od, const WavePlan &w
   }
 }
 
+// Persistent solves of several groups run concurrently, each in its own
+// workspace region; otherwise groups share one region and run in turn.
+static bool concurrent_groups(int32_t n_groups, const psr_solve_opts *o) {
+  return n_groups > 1 && o->scheduler == PSR_PERSISTENT;
+}
+
 // Workspace of one group: states [B], plain-scheduler areas [B][persist],
 // counters.
 static size_t group_ws(const psr_group &g, const psr_solve_opts *o) {
@@ -909,12 +915,14 @@ static size_t group_ws(const psr_group &g, const psr_solve_opts *o) {
 extern "C" size_t psr_workspace_bytes(const psr_group *groups, int32_t n_groups,
                                       const psr_solve_opts *opts) {
   if (!groups || n_groups <= 0 || !opts) return 0;
-  size_t mx = 0;
+  size_t mx = 0, sum = 0;
   for (int gi = 0; gi < n_groups; gi++) {
     if (!groups[gi].mech || groups[gi].cond.n_reactors <= 0) return 0;
-    mx = std::max(mx, group_ws(groups[gi], opts));
+    const size_t b = group_ws(groups[gi], opts);
+    mx = std::max(mx, b);
+    sum += align256(b);
   }
-  return mx;
+  return concurrent_groups(n_groups, opts) ? sum : mx;
 }
 
 static psr_status check_opts(const psr_solve_opts *o) {
@@ -930,41 +938,60 @@ static psr_status check_opts(const psr_solve_opts *o) {
 }
 
 
-static psr_status solve_group(const psr_group &g, const psr_solve_opts *o, void *ws, hipStream_t stream,
-                              psr_solve_stats *acc) {
-  const bool mixed = o->precision == PSR_MIXED;
-  const int64_t B = g.cond.n_reactors;
-  Layout L;
-  const bool fits = block_layout(g.mech, g.cond.energy, mixed, L);
-  const size_t lds = (size_t)L.total * 8;
-  const WavePlan wplan = wave_plan(g.mech, g.cond.energy, mixed, o->engine);
-  if (o->engine == 2 && !wplan.NP)
-    return fail(PSR_EUNSUPPORTED, "wavefront engine needs n <= 64 and a mechanism that fits its LDS");
-  if (!wplan.NP && !fits)
-    return fail(PSR_EUNSUPPORTED, "reactor working set (" + std::to_string(lds) +
-                                      " B without matrices) exceeds the LDS of one workgroup");
+// One group of a solve: its device view, engine plan and workspace region.
+struct GroupRun {
   GroupDev gd;
-  gd.m = g.mech->dev; gd.energy = g.cond.energy ? 1 : 0; gd.B = B;
+  Layout L;
+  WavePlan wplan;
+  size_t lds = 0;
+  bool mixed = false;
+  RState *states = nullptr;
+  int *counters = nullptr;
+  double *area = nullptr;
+  int rounds = 0;
+};
+
+static psr_status prepare_group(const psr_group &g, const psr_solve_opts *o, void *ws, GroupRun &r) {
+  r.mixed = o->precision == PSR_MIXED;
+  const bool fits = block_layout(g.mech, g.cond.energy, r.mixed, r.L);
+  r.lds = (size_t)r.L.total * 8;
+  r.wplan = wave_plan(g.mech, g.cond.energy, r.mixed, o->engine);
+  if (o->engine == 2 && !r.wplan.NP)
+    return fail(PSR_EUNSUPPORTED, "wavefront engine needs n <= 64 and a mechanism that fits its LDS");
+  if (!r.wplan.NP && !fits)
+    return fail(PSR_EUNSUPPORTED, "reactor working set (" + std::to_string(r.lds) +
+                                      " B without matrices) exceeds the LDS of one workgroup");
+  GroupDev &gd = r.gd;
+  gd.m = g.mech->dev; gd.energy = g.cond.energy ? 1 : 0; gd.B = g.cond.n_reactors;
   gd.P = g.cond.P; gd.tau = g.cond.tau; gd.Tin = g.cond.T_in; gd.Yin = g.cond.Y_in;
   gd.x = g.x_inout; gd.status = g.status; gd.nlin = g.n_lin;
-  const Opts od = to_dev_opts(o);
   char *p = reinterpret_cast<char *>(ws);
-  RState *states = reinterpret_cast<RState *>(p);
-  p += align256(sizeof(RState) * (size_t)B);
-  int *counters = reinterpret_cast<int *>(p);
+  r.states = reinterpret_cast<RState *>(p);
+  p += align256(sizeof(RState) * (size_t)gd.B);
+  r.counters = reinterpret_cast<int *>(p);
   p += 256;
-  double *area = reinterpret_cast<double *>(p);
+  r.area = reinterpret_cast<double *>(p);
+  return PSR_OK;
+}
 
-  hipEvent_t e0, e1;
-  HIP_OK(hipEventCreate(&e0));
-  HIP_OK(hipEventCreate(&e1));
-  HIP_OK(hipEventRecord(e0, stream));
-  int rounds = 0;
-  if (wplan.NP) {
-    const psr_status st = run_wave(gd, od, wplan, mixed, o->scheduler, states, counters, area, stream,
-                                   o->max_lin * 2 + 8, &rounds);
-    if (st != PSR_OK) return st;
-  } else if (o->scheduler == PSR_PERSISTENT) {
+// Issue the group's launches on `stream`.  Persistent scheduler: returns
+// after the launches (asynchronous).  Plain scheduler: drives the rounds from
+// the host and returns when every reactor has retired.
+static psr_status launch_group(GroupRun &r, const psr_solve_opts *o, hipStream_t stream) {
+  const Opts od = to_dev_opts(o);
+  const GroupDev &gd = r.gd;
+  const int64_t B = gd.B;
+  const bool mixed = r.mixed;
+  const Layout &L = r.L;
+  const size_t lds = r.lds;
+  RState *states = r.states;
+  int *counters = r.counters;
+  double *area = r.area;
+  r.rounds = 0;
+  if (r.wplan.NP)
+    return run_wave(gd, od, r.wplan, mixed, o->scheduler, states, counters, area, stream, o->max_lin * 2 + 8,
+                    &r.rounds);
+  if (o->scheduler == PSR_PERSISTENT) {
     const int64_t grid = block_grid(L, mixed, B);
     if (grid <= 0) return fail(PSR_EDEVICE, "occupancy query failed");
     double *matws = L.split ? area : nullptr;  // one HBM matrix area per resident workgroup
@@ -976,54 +1003,66 @@ static psr_status solve_group(const psr_group &g, const psr_solve_opts *o, void 
       hipLaunchKernelGGL(k_persistent<false>, dim3((unsigned)grid), dim3(kBS), lds, stream, gd, od, states,
                          counters, matws);
     HIP_OK(hipGetLastError());
-  } else {
-    const int check_every = 4;
-    if (mixed)
-      hipLaunchKernelGGL((k_round<true, true>), dim3((unsigned)B), dim3(kBS), lds, stream, gd, od, states,
-                         area, L.split, counters);
-    else
-      hipLaunchKernelGGL((k_round<false, true>), dim3((unsigned)B), dim3(kBS), lds, stream, gd, od, states,
-                         area, L.split, counters);
+    return PSR_OK;
+  }
+  const int check_every = 4;
+  if (mixed)
+    hipLaunchKernelGGL((k_round<true, true>), dim3((unsigned)B), dim3(kBS), lds, stream, gd, od, states,
+                       area, L.split, counters);
+  else
+    hipLaunchKernelGGL((k_round<false, true>), dim3((unsigned)B), dim3(kBS), lds, stream, gd, od, states,
+                       area, L.split, counters);
+  HIP_OK(hipGetLastError());
+  int active = 1;
+  const int max_rounds = o->max_lin * 2 + 8;
+  while (active > 0 && r.rounds < max_rounds) {
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, counters, 1);
+    for (int k = 0; k < check_every; k++) {
+      if (mixed)
+        hipLaunchKernelGGL((k_round<true, false>), dim3((unsigned)B), dim3(kBS), lds, stream, gd, od,
+                           states, area, L.split, counters);
+      else
+        hipLaunchKernelGGL((k_round<false, false>), dim3((unsigned)B), dim3(kBS), lds, stream, gd, od,
+                           states, area, L.split, counters);
+      r.rounds++;
+    }
     HIP_OK(hipGetLastError());
-    int active = 1;
-    const int max_rounds = o->max_lin * 2 + 8;
-    while (active > 0 && rounds < max_rounds) {
-      hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, counters, 1);
-      for (int r = 0; r < check_every; r++) {
-        if (mixed)
-          hipLaunchKernelGGL((k_round<true, false>), dim3((unsigned)B), dim3(kBS), lds, stream, gd, od,
-                             states, area, L.split, counters);
-        else
-          hipLaunchKernelGGL((k_round<false, false>), dim3((unsigned)B), dim3(kBS), lds, stream, gd, od,
-                             states, area, L.split, counters);
-        rounds++;
-      }
-      HIP_OK(hipGetLastError());
-      HIP_OK(hipMemcpyAsync(&active, counters, sizeof(int), hipMemcpyDeviceToHost, stream));
-      HIP_OK(hipStreamSynchronize(stream));
-    }
-    if (active > 0) return fail(PSR_EDEVICE, "plain scheduler did not retire every reactor");
+    HIP_OK(hipMemcpyAsync(&active, counters, sizeof(int), hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipStreamSynchronize(stream));
   }
-  HIP_OK(hipEventRecord(e1, stream));
-  HIP_OK(hipEventSynchronize(e1));
-  float ms = 0.f;
-  HIP_OK(hipEventElapsedTime(&ms, e0, e1));
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  if (acc) {
-    std::vector<RState> hs(B);
-    HIP_OK(hipMemcpy(hs.data(), states, sizeof(RState) * B, hipMemcpyDeviceToHost));
-    acc->reactors += B;
-    for (const RState &s : hs) {
-      acc->converged += s.status == RS_CONVERGED;
-      acc->lin_total += s.n_lin;
-      acc->lin_max = std::max<int64_t>(acc->lin_max, s.n_lin);
-      acc->jac_total += s.n_jac;
-      acc->fp64_fallbacks += s.n_fb64;
-    }
-    acc->rounds += rounds;
-    acc->kernel_ms += ms;
+  if (active > 0) return fail(PSR_EDEVICE, "plain scheduler did not retire every reactor");
+  return PSR_OK;
+}
+
+static psr_status collect_group(const GroupRun &r, psr_solve_stats *acc) {
+  if (!acc) return PSR_OK;
+  const int64_t B = r.gd.B;
+  std::vector<RState> hs(B);
+  HIP_OK(hipMemcpy(hs.data(), r.states, sizeof(RState) * B, hipMemcpyDeviceToHost));
+  acc->reactors += B;
+  for (const RState &s : hs) {
+    acc->converged += s.status == RS_CONVERGED;
+    acc->lin_total += s.n_lin;
+    acc->lin_max = std::max<int64_t>(acc->lin_max, s.n_lin);
+    acc->jac_total += s.n_jac;
+    acc->fp64_fallbacks += s.n_fb64;
   }
+  acc->rounds += r.rounds;
+  return PSR_OK;
+}
+
+// Streams on which the groups of one persistent solve run side by side
+// (default priority), created on first use and kept for the process.
+static psr_status group_stream(int dev, int i, hipStream_t *out) {
+  static std::vector<std::vector<hipStream_t>> pool;
+  if ((int)pool.size() <= dev) pool.resize(dev + 1);
+  auto &v = pool[dev];
+  while ((int)v.size() <= i) {
+    hipStream_t s;
+    HIP_OK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    v.push_back(s);
+  }
+  *out = v[i];
   return PSR_OK;
 }
 
@@ -1042,9 +1081,53 @@ extern "C" psr_status psr_solve_batch(const psr_group *groups, int32_t n_groups,
   if (!workspace || workspace_bytes < need)
     return fail(PSR_ENOMEM, "workspace smaller than psr_workspace_bytes() = " + std::to_string(need));
   if (stats) memset(stats, 0, sizeof(*stats));
+  const hipStream_t cs = (hipStream_t)stream;
+  const bool conc = concurrent_groups(n_groups, opts);
+  std::vector<GroupRun> runs(n_groups);
+  char *region = reinterpret_cast<char *>(workspace);
   for (int gi = 0; gi < n_groups; gi++) {
-    st = solve_group(groups[gi], opts, workspace, (hipStream_t)stream, stats);
+    st = prepare_group(groups[gi], opts, region, runs[gi]);
+    if (st != PSR_OK) return st;
+    if (conc) region += align256(group_ws(groups[gi], opts));
+  }
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  HIP_OK(hipEventRecord(e0, cs));
+  if (conc) {
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    std::vector<hipEvent_t> done(n_groups);
+    for (int gi = 0; gi < n_groups; gi++) {
+      hipStream_t gs;
+      st = group_stream(dev, gi, &gs);
+      if (st != PSR_OK) return st;
+      HIP_OK(hipStreamWaitEvent(gs, e0, 0));
+      st = launch_group(runs[gi], opts, gs);
+      if (st != PSR_OK) return st;
+      HIP_OK(hipEventCreateWithFlags(&done[gi], hipEventDisableTiming));
+      HIP_OK(hipEventRecord(done[gi], gs));
+      HIP_OK(hipStreamWaitEvent(cs, done[gi], 0));
+    }
+    HIP_OK(hipEventRecord(e1, cs));
+    HIP_OK(hipEventSynchronize(e1));
+    for (hipEvent_t e : done) hipEventDestroy(e);
+  } else {
+    for (int gi = 0; gi < n_groups; gi++) {
+      st = launch_group(runs[gi], opts, cs);
+      if (st != PSR_OK) return st;
+    }
+    HIP_OK(hipEventRecord(e1, cs));
+    HIP_OK(hipEventSynchronize(e1));
+  }
+  float ms = 0.f;
+  HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  for (int gi = 0; gi < n_groups; gi++) {
+    st = collect_group(runs[gi], stats);
     if (st != PSR_OK) return st;
   }
+  if (stats) stats->kernel_ms = ms;
   return PSR_OK;
 }

@@ -103,3 +103,14 @@ def test_uneven_schedulers_agree_bitwise(P, groups):
     for (xa, sa, na), (xb, sb, nb) in zip(a, b):
         assert np.array_equal(sa, sb) and np.array_equal(na, nb)
         assert np.array_equal(xa, xb)
+
+
+def test_concurrent_groups_match_separate_calls(P, groups):
+    """Groups of one persistent call run side by side on library streams; the
+    results equal those of one call per group, bit for bit."""
+    sub = [g for g in groups if g[0] != "uneven_b"]
+    together, _ = _solve_all(P, sub, precision=0, scheduler=P.PSR_PERSISTENT)
+    for g, (xa, sa, na) in zip(sub, together):
+        (xb, sb, nb), = _solve_all(P, [g], precision=0, scheduler=P.PSR_PERSISTENT)[0]
+        assert np.array_equal(sa, sb) and np.array_equal(na, nb)
+        assert np.array_equal(xa, xb)
