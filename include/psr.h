@@ -147,9 +147,14 @@ typedef struct {
    * of 256 threads per reactor, 2 one wavefront per reactor (PSR_EUNSUPPORTED
    * if it does not fit). Results agree to rounding, not bitwise. */
   int32_t engine;
+  /* plain scheduler: 1 replays the rounds between two host checks as one
+   * captured HIP graph on a library stream (ordered after `stream`), 0
+   * launches them one by one on `stream`.  Results are identical. */
+  int32_t use_graph;
 } psr_solve_opts;
 
-/* Fill opts with the defaults (FP64, plain scheduler, tolerances above). */
+/* Fill opts with the defaults (FP64, plain scheduler, graph replay on,
+ * automatic engine, tolerances above). */
 void psr_default_opts(psr_solve_opts *opts);
 
 /* One mechanism's reactors in a solve.  Device pointers. */

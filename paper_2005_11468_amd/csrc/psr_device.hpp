@@ -462,7 +462,7 @@ __device__ int lu_factor(T *A, int n, int lda, int *piv, double *red) {
 //             read from the panel in LDS;
 //   A22:      A22 -= L21 U12 on the matrix cores, v_mfma_f32_16x16x4f32 per
 //             16 x 16 tile and K step of 4; each wavefront takes every fourth
-//             tile row and sweeps its tile columns eight at a time.
+//             tile row and sweeps its tile columns four at a time.
 // Operand layouts of the 16x16x4 instruction (lane l): A(l % 16, l / 16),
 // B(l / 16, l % 16), D[v](4 (l / 16) + v, l % 16).  Same factor format as
 // lu_factor (unit-lower L below the diagonal, LAPACK pivots).  BS must be
@@ -522,24 +522,27 @@ __device__ __forceinline__ int lu_factor_mfma32(float *A, int n, int lda, int *p
       const int t = e >> 4, j = e & 15;
       if (j < kb) A[(int64_t)(k0 + t) * lda + k0 + j] = pan[t * PS + j];
     }
-    // the panel's interchanges on the other columns, in order
-    for (int c = tid; c < n; c += BS) {
-      if (c >= k0 && c < k0 + kb) continue;
-      for (int jj = 0; jj < kb; jj++) {
-        const int pr = piv[k0 + jj];
-        if (pr != k0 + jj) {
-          float *x = A + (int64_t)(k0 + jj) * lda + c, *y = A + (int64_t)pr * lda + c;
-          const float t = *x;
-          *x = *y;
-          *y = t;
+    // the panel's interchanges on the other columns, in order (n <= BS: at
+    // most one column per thread)
+    {
+      const int c = tid;
+      if (c < n && (c < k0 || c >= k0 + kb))
+        for (int jj = 0; jj < kb; jj++) {
+          const int pr = piv[k0 + jj];
+          if (pr != k0 + jj) {
+            float *x = A + (int64_t)(k0 + jj) * lda + c, *y = A + (int64_t)pr * lda + c;
+            const float t = *x;
+            *x = *y;
+            *y = t;
+          }
         }
-      }
     }
     __syncthreads();
     const int R0 = k0 + kb, m = n - R0;
     if (m <= 0) break;
-    // U12 = L11^-1 A12
-    for (int c = R0 + tid; c < n; c += BS) {
+    // U12 = L11^-1 A12 (one column per thread)
+    if (R0 + tid < n) {
+      const int c = R0 + tid;
       float u[16];
 #pragma unroll
       for (int i = 0; i < 16; i++) u[i] = i < kb ? A[(int64_t)(k0 + i) * lda + c] : 0.f;
@@ -556,7 +559,7 @@ __device__ __forceinline__ int lu_factor_mfma32(float *A, int n, int lda, int *p
         if (i < kb) A[(int64_t)(k0 + i) * lda + c] = u[i];
     }
     __syncthreads();
-    // A22 -= L21 U12 on the matrix cores, eight tile columns at a time
+    // A22 -= L21 U12 on the matrix cores, four tile columns at a time
     const int nt = (m + 15) / 16;
     const int lr = lane & 15, lk = lane >> 4;
     for (int ti = wv; ti < nt; ti += BS / 64) {
@@ -568,11 +571,11 @@ __device__ __forceinline__ int lu_factor_mfma32(float *A, int n, int lda, int *p
         aq[q] = (arow < n && k < kb) ? -A[(int64_t)arow * lda + k0 + k] : 0.f;
       }
       const int crow = R0 + 16 * ti + 4 * lk;
-      for (int tj0 = 0; tj0 < nt; tj0 += 8) {
-        float bq[8][4];
-        v4f acc[8];
+      for (int tj0 = 0; tj0 < nt; tj0 += 4) {
+        float bq[4][4];
+        v4f acc[4];
 #pragma unroll
-        for (int t = 0; t < 8; t++) {
+        for (int t = 0; t < 4; t++) {
           const int col = R0 + 16 * (tj0 + t) + lr;
           const bool cin = (tj0 + t) < nt && col < n;
 #pragma unroll
@@ -584,11 +587,11 @@ __device__ __forceinline__ int lu_factor_mfma32(float *A, int n, int lda, int *p
           for (int v = 0; v < 4; v++) acc[t][v] = (cin && crow + v < n) ? A[(int64_t)(crow + v) * lda + col] : 0.f;
         }
 #pragma unroll
-        for (int t = 0; t < 8; t++)
+        for (int t = 0; t < 4; t++)
 #pragma unroll
           for (int q = 0; q < 4; q++) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(aq[q], bq[t][q], acc[t], 0, 0, 0);
 #pragma unroll
-        for (int t = 0; t < 8; t++) {
+        for (int t = 0; t < 4; t++) {
           const int col = R0 + 16 * (tj0 + t) + lr;
           if ((tj0 + t) < nt && col < n) {
 #pragma unroll

@@ -192,7 +192,7 @@ __device__ inline void write_result(const GroupDev &g, const Ctx &c, const RStat
 
 // Plain scheduler: one round per launch.  The persistent part of each
 // reactor's area lives in HBM (`area`, [B][persist]) between launches.
-template <bool MIXED, bool FIRST>
+template <bool MIXED, bool FIRST, bool BIG>
 __global__ void __launch_bounds__(kBS) k_round(GroupDev g, Opts o, RState *states, double *area,
                                                int split, int *active) {
   extern __shared__ double lds[];
@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(kBS) k_round(GroupDev g, Opts o, RState *state
   } else {
     for (int e = threadIdx.x; e < persist; e += kBS) lds[e] = mine[e];
     __syncthreads();
-    round_step<kBS, MIXED>(c, o, s);
+    round_step<kBS, MIXED, BIG>(c, o, s);
   }
   if (s.phase == PH_DONE) {
     write_result(g, c, s, b);
@@ -228,7 +228,7 @@ __global__ void __launch_bounds__(kBS) k_round(GroupDev g, Opts o, RState *state
 // Persistent scheduler: grid sized to the resident capacity; each
 // workgroup takes the next reactor index from `queue` until none is left,
 // and runs it to completion with every array in LDS.
-template <bool MIXED>
+template <bool MIXED, bool BIG>
 __global__ void __launch_bounds__(kBS) k_persistent(GroupDev g, Opts o, RState *states, int *queue,
                                                     double *matws) {
   extern __shared__ double lds[];
@@ -249,7 +249,7 @@ __global__ void __launch_bounds__(kBS) k_persistent(GroupDev g, Opts o, RState *
     __syncthreads();
     RState s;
     init_state<kBS>(c, o, s);
-    while (s.phase != PH_DONE) round_step<kBS, MIXED>(c, o, s);
+    while (s.phase != PH_DONE) round_step<kBS, MIXED, BIG>(c, o, s);
     write_result(g, c, s, b);
     if (threadIdx.x == 0) states[b] = s;
     __syncthreads();
@@ -484,6 +484,7 @@ extern "C" void psr_default_opts(psr_solve_opts *o) {
   o->max_lin = 1000;
   o->max_refine = 6;
   o->engine = 0;
+  o->use_graph = 1;
 }
 
 extern "C" psr_status psr_create_mechanism(const psr_mech_desc *d, psr_mech_t *out) {
@@ -656,12 +657,18 @@ static bool block_layout(psr_mech_t m, int energy, bool mixed, Layout &L) {
 
 // Resident workgroups of the block engine's persistent kernel.
 static int64_t block_grid(const Layout &L, bool mixed, int64_t B) {
+  const bool big = L.n > 64;
   int dev = 0, ncu = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
   const size_t lds = (size_t)L.total * 8;
-  hipError_t e = mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<true>, kBS, lds)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<false>, kBS, lds);
+  hipError_t e;
+  if (mixed)
+    e = big ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<true, true>, kBS, lds)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<true, false>, kBS, lds);
+  else
+    e = big ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<false, true>, kBS, lds)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<false, false>, kBS, lds);
   if (e != hipSuccess) return 0;
   if (per_cu < 1) per_cu = 1;
   return std::min<int64_t>(B, (int64_t)ncu * per_cu);
@@ -832,10 +839,71 @@ static WavePlan wave_plan(psr_mech_t m, int energy, bool mixed, int engine) {
   return w;
 }
 
+// Streams on which the groups of one persistent solve run side by side
+// (default priority), created on first use and kept for the process.
+static psr_status group_stream(int dev, int i, hipStream_t *out) {
+  static std::vector<std::vector<hipStream_t>> pool;
+  if ((int)pool.size() <= dev) pool.resize(dev + 1);
+  auto &v = pool[dev];
+  while ((int)v.size() <= i) {
+    hipStream_t s;
+    HIP_OK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    v.push_back(s);
+  }
+  *out = v[i];
+  return PSR_OK;
+}
+
+// Drives the plain scheduler after its first round: `period(s)` enqueues one
+// check period (counter reset + `per` rounds) on stream s; the host reads the
+// active count after each period.  With use_graph the period is captured once
+// as a HIP graph on a library stream (after the work already on `stream`) and
+// replayed; the counter reset is a kernel, not a memset node.
+template <typename F>
+static psr_status drive_plain(hipStream_t stream, bool use_graph, int *counters, int per, int max_rounds,
+                              F period, int *rounds_out) {
+  int active = 1, rounds = 0;
+  hipStream_t s = stream;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev = nullptr;
+  if (use_graph) {
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    const psr_status st = group_stream(dev, 0, &s);
+    if (st != PSR_OK) return st;
+    HIP_OK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIP_OK(hipEventRecord(ev, stream));
+    HIP_OK(hipStreamWaitEvent(s, ev, 0));
+    HIP_OK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    period(s);
+    HIP_OK(hipStreamEndCapture(s, &graph));
+    HIP_OK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  }
+  while (active > 0 && rounds < max_rounds) {
+    if (exec) HIP_OK(hipGraphLaunch(exec, s));
+    else period(s);
+    rounds += per;
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(&active, counters, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+  }
+  if (exec) {
+    HIP_OK(hipGraphExecDestroy(exec));
+    HIP_OK(hipGraphDestroy(graph));
+    HIP_OK(hipEventRecord(ev, s));
+    HIP_OK(hipStreamWaitEvent(stream, ev, 0));
+    HIP_OK(hipEventDestroy(ev));
+  }
+  *rounds_out = rounds;
+  if (active > 0) return fail(PSR_EDEVICE, "plain scheduler did not retire every reactor");
+  return PSR_OK;
+}
+
 template <int NP, bool MIXED>
 static psr_status launch_wave(const GroupDev &gd, const Opts &od, const WavePlan &w, int scheduler,
                               RState *states, int *counters, double *area, hipStream_t stream,
-                              int max_rounds, int *rounds_out) {
+                              int max_rounds, int *rounds_out, bool use_graph) {
   const int64_t B = gd.B;
   const int threads = 64 * w.rpw;
   if (scheduler == PSR_PERSISTENT) {
@@ -857,37 +925,29 @@ static psr_status launch_wave(const GroupDev &gd, const Opts &od, const WavePlan
   hipLaunchKernelGGL((wk::k_wround<NP, MIXED, true>), dim3(grid), dim3(threads), w.lds, stream, gd, od, states,
                      area, w.stride, w.rpw, counters);
   HIP_OK(hipGetLastError());
-  int active = 1, rounds = 0;
   const int check_every = 4;
-  while (active > 0 && rounds < max_rounds) {
-    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, counters, 1);
-    for (int r = 0; r < check_every; r++) {
-      hipLaunchKernelGGL((wk::k_wround<NP, MIXED, false>), dim3(grid), dim3(threads), w.lds, stream, gd, od,
-                         states, area, w.stride, w.rpw, counters);
-      rounds++;
-    }
-    HIP_OK(hipGetLastError());
-    HIP_OK(hipMemcpyAsync(&active, counters, sizeof(int), hipMemcpyDeviceToHost, stream));
-    HIP_OK(hipStreamSynchronize(stream));
-  }
-  *rounds_out = rounds;
-  if (active > 0) return fail(PSR_EDEVICE, "plain scheduler did not retire every reactor");
-  return PSR_OK;
+  auto period = [&](hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, counters, 1);
+    for (int r = 0; r < check_every; r++)
+      hipLaunchKernelGGL((wk::k_wround<NP, MIXED, false>), dim3(grid), dim3(threads), w.lds, s, gd, od, states,
+                         area, w.stride, w.rpw, counters);
+  };
+  return drive_plain(stream, use_graph, counters, check_every, max_rounds, period, rounds_out);
 }
 
 static psr_status run_wave(const GroupDev &gd, const Opts &od, const WavePlan &w, bool mixed, int scheduler,
                            RState *states, int *counters, double *area, hipStream_t stream, int max_rounds,
-                           int *rounds) {
+                           int *rounds, bool use_graph) {
   switch (w.NP) {
     case 16:
-      return mixed ? launch_wave<16, true>(gd, od, w, scheduler, states, counters, area, stream, max_rounds, rounds)
-                   : launch_wave<16, false>(gd, od, w, scheduler, states, counters, area, stream, max_rounds, rounds);
+      return mixed ? launch_wave<16, true>(gd, od, w, scheduler, states, counters, area, stream, max_rounds, rounds, use_graph)
+                   : launch_wave<16, false>(gd, od, w, scheduler, states, counters, area, stream, max_rounds, rounds, use_graph);
     case 32:
-      return mixed ? launch_wave<32, true>(gd, od, w, scheduler, states, counters, area, stream, max_rounds, rounds)
-                   : launch_wave<32, false>(gd, od, w, scheduler, states, counters, area, stream, max_rounds, rounds);
+      return mixed ? launch_wave<32, true>(gd, od, w, scheduler, states, counters, area, stream, max_rounds, rounds, use_graph)
+                   : launch_wave<32, false>(gd, od, w, scheduler, states, counters, area, stream, max_rounds, rounds, use_graph);
     default:
-      return mixed ? launch_wave<64, true>(gd, od, w, scheduler, states, counters, area, stream, max_rounds, rounds)
-                   : launch_wave<64, false>(gd, od, w, scheduler, states, counters, area, stream, max_rounds, rounds);
+      return mixed ? launch_wave<64, true>(gd, od, w, scheduler, states, counters, area, stream, max_rounds, rounds, use_graph)
+                   : launch_wave<64, false>(gd, od, w, scheduler, states, counters, area, stream, max_rounds, rounds, use_graph);
   }
 }
 
@@ -932,7 +992,8 @@ static psr_status check_opts(const psr_solve_opts *o) {
   if (!(o->rtol > 0) || !(o->atol_Y >= 0) || !(o->atol_T >= 0) || !(o->ftol > 0) ||
       !(o->lambda_min > 0 && o->lambda_min <= 1) || !(o->T_min < o->T_max) || !(o->ts_rtol > 0) ||
       !(o->h0 > 0) || !(o->h_min > 0) || !(o->h_max > 0) || o->nw_max_it < 1 || o->nw_every < 1 ||
-      o->max_lin < 1 || o->max_refine < 0 || o->engine < 0 || o->engine > 2)
+      o->max_lin < 1 || o->max_refine < 0 || o->engine < 0 || o->engine > 2 || o->use_graph < 0 ||
+      o->use_graph > 1)
     return fail(PSR_EINVAL, "option out of range");
   return PSR_OK;
 }
@@ -990,48 +1051,51 @@ static psr_status launch_group(GroupRun &r, const psr_solve_opts *o, hipStream_t
   r.rounds = 0;
   if (r.wplan.NP)
     return run_wave(gd, od, r.wplan, mixed, o->scheduler, states, counters, area, stream, o->max_lin * 2 + 8,
-                    &r.rounds);
+                    &r.rounds, o->use_graph != 0);
   if (o->scheduler == PSR_PERSISTENT) {
     const int64_t grid = block_grid(L, mixed, B);
     if (grid <= 0) return fail(PSR_EDEVICE, "occupancy query failed");
     double *matws = L.split ? area : nullptr;  // one HBM matrix area per resident workgroup
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, counters, 64);
-    if (mixed)
-      hipLaunchKernelGGL(k_persistent<true>, dim3((unsigned)grid), dim3(kBS), lds, stream, gd, od, states,
+    const bool big = L.n > 64;
+    if (mixed && big)
+      hipLaunchKernelGGL((k_persistent<true, true>), dim3((unsigned)grid), dim3(kBS), lds, stream, gd, od, states,
                          counters, matws);
+    else if (mixed)
+      hipLaunchKernelGGL((k_persistent<true, false>), dim3((unsigned)grid), dim3(kBS), lds, stream, gd, od,
+                         states, counters, matws);
+    else if (big)
+      hipLaunchKernelGGL((k_persistent<false, true>), dim3((unsigned)grid), dim3(kBS), lds, stream, gd, od,
+                         states, counters, matws);
     else
-      hipLaunchKernelGGL(k_persistent<false>, dim3((unsigned)grid), dim3(kBS), lds, stream, gd, od, states,
-                         counters, matws);
+      hipLaunchKernelGGL((k_persistent<false, false>), dim3((unsigned)grid), dim3(kBS), lds, stream, gd, od,
+                         states, counters, matws);
     HIP_OK(hipGetLastError());
     return PSR_OK;
   }
   const int check_every = 4;
-  if (mixed)
-    hipLaunchKernelGGL((k_round<true, true>), dim3((unsigned)B), dim3(kBS), lds, stream, gd, od, states,
-                       area, L.split, counters);
-  else
-    hipLaunchKernelGGL((k_round<false, true>), dim3((unsigned)B), dim3(kBS), lds, stream, gd, od, states,
-                       area, L.split, counters);
-  HIP_OK(hipGetLastError());
-  int active = 1;
-  const int max_rounds = o->max_lin * 2 + 8;
-  while (active > 0 && r.rounds < max_rounds) {
-    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, counters, 1);
-    for (int k = 0; k < check_every; k++) {
-      if (mixed)
-        hipLaunchKernelGGL((k_round<true, false>), dim3((unsigned)B), dim3(kBS), lds, stream, gd, od,
-                           states, area, L.split, counters);
-      else
-        hipLaunchKernelGGL((k_round<false, false>), dim3((unsigned)B), dim3(kBS), lds, stream, gd, od,
-                           states, area, L.split, counters);
-      r.rounds++;
+  const bool big = L.n > 64;
+  // k_round<MIXED, FIRST, BIG>
+  auto launch_round = [&](hipStream_t s, bool first) {
+#define PSR_ROUND(M, F, G)                                                                                    \
+  hipLaunchKernelGGL((k_round<M, F, G>), dim3((unsigned)B), dim3(kBS), lds, s, gd, od, states, area, L.split, \
+                     counters)
+    if (mixed) {
+      if (first) { if (big) PSR_ROUND(true, true, true); else PSR_ROUND(true, true, false); }
+      else { if (big) PSR_ROUND(true, false, true); else PSR_ROUND(true, false, false); }
+    } else {
+      if (first) { if (big) PSR_ROUND(false, true, true); else PSR_ROUND(false, true, false); }
+      else { if (big) PSR_ROUND(false, false, true); else PSR_ROUND(false, false, false); }
     }
-    HIP_OK(hipGetLastError());
-    HIP_OK(hipMemcpyAsync(&active, counters, sizeof(int), hipMemcpyDeviceToHost, stream));
-    HIP_OK(hipStreamSynchronize(stream));
-  }
-  if (active > 0) return fail(PSR_EDEVICE, "plain scheduler did not retire every reactor");
-  return PSR_OK;
+#undef PSR_ROUND
+  };
+  launch_round(stream, true);
+  HIP_OK(hipGetLastError());
+  auto period = [&](hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, counters, 1);
+    for (int k = 0; k < check_every; k++) launch_round(s, false);
+  };
+  return drive_plain(stream, o->use_graph != 0, counters, check_every, o->max_lin * 2 + 8, period, &r.rounds);
 }
 
 static psr_status collect_group(const GroupRun &r, psr_solve_stats *acc) {
@@ -1051,20 +1115,6 @@ static psr_status collect_group(const GroupRun &r, psr_solve_stats *acc) {
   return PSR_OK;
 }
 
-// Streams on which the groups of one persistent solve run side by side
-// (default priority), created on first use and kept for the process.
-static psr_status group_stream(int dev, int i, hipStream_t *out) {
-  static std::vector<std::vector<hipStream_t>> pool;
-  if ((int)pool.size() <= dev) pool.resize(dev + 1);
-  auto &v = pool[dev];
-  while ((int)v.size() <= i) {
-    hipStream_t s;
-    HIP_OK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-    v.push_back(s);
-  }
-  *out = v[i];
-  return PSR_OK;
-}
 
 extern "C" psr_status psr_solve_batch(const psr_group *groups, int32_t n_groups, const psr_solve_opts *opts,
                                       void *workspace, size_t workspace_bytes, psr_solve_stats *stats,

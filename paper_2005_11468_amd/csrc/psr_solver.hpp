@@ -72,7 +72,7 @@ __device__ inline int matrix_finite(const double *A, int n, int lda, double *red
 // Mixed precision: scale rows, then columns, of A64 by powers of two (exact)
 // so every row and column has max magnitude in [1/2, 1), round to float into
 // A32 and factor there.  Returns the float LU's status.
-template <int BS>
+template <int BS, bool BIG>
 __device__ int factor_mixed(const Ctx &c, const double *A64, float *A32, int *piv, double *rs,
                             double *cs, double *red) {
   const int n = c.n, lda = c.L.lda;
@@ -99,7 +99,7 @@ __device__ int factor_mixed(const Ctx &c, const double *A64, float *A32, int *pi
   __syncthreads();
   // large matrices: blocked matrix-core LU; its panel borrows the reaction
   // scratch in LDS (not in use between the Jacobian and the next residual)
-  if (BS == 256 && n > 64 && n <= 256 && 12 * c.L.I * 2 >= 17 * n)
+  if (BIG && BS == 256 && n > 64 && n <= 256 && 12 * c.L.I * 2 >= 17 * n)
     return lu_factor_mfma32<256>(A32, n, lda, piv, red, reinterpret_cast<float *>(c.p(c.L.kf)));
   return lu_factor<BS, float>(A32, n, lda, piv, red);
 }
@@ -219,7 +219,7 @@ __device__ inline void reject_ts(const Ctx &c, const Opts &o, RState &s, bool ba
 }
 
 // One round of the controller.
-template <int BS, bool MIXED>
+template <int BS, bool MIXED, bool BIG>
 __device__ void round_step(Ctx &c, const Opts &o, RState &s) {
   const Layout &L = c.L;
   const int n = c.n, N = c.N, lda = L.lda;
@@ -244,7 +244,7 @@ __device__ void round_step(Ctx &c, const Opts &o, RState &s) {
     s.sing = 0;
     if (s.fin) {
       if (MIXED) {
-        const int info = factor_mixed<BS>(c, A64, c.A32(), piv,
+        const int info = factor_mixed<BS, BIG>(c, A64, c.A32(), piv,
                                           c.p(L.rs), c.p(L.cs), red);
         if (info != 0) {
           s.fb64 = 1;
