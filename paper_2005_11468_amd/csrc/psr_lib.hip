@@ -432,7 +432,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
 // so the tables are staged once per workgroup.
 constexpr int kWR = 8;
 
-__global__ void __launch_bounds__(kWR * 64) k_wresidual(GroupDev g, double *F, double *scaled) {
+__global__ void __launch_bounds__(kWR * 64) __attribute__((amdgpu_waves_per_eu(6)))
+k_wresidual(GroupDev g, double *F, double *scaled) {
   extern __shared__ double lds[];
   char *base = reinterpret_cast<char *>(lds);
   const Tables t = stage_tables(g.m, base, g.m.packed);

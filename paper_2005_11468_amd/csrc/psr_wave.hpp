@@ -126,13 +126,14 @@ struct WArea {
     Cs = p; p += WS; gs = p; p += WS; hs = p; p += WS; iSW = p; p += WS; rW = p; p += WS;
     cs = p; p += WS; zs = p;
   }
-  // Species scratch only (no Jacobian rows): residual evaluation.
-  static __host__ __device__ int species_doubles() { return 8 * WS; }
+  // Species scratch of a residual evaluation only (C, g, H/RT and the two
+  // accumulators; no Jacobian rows or Jacobian scratch).
+  static __host__ __device__ int species_doubles() { return 5 * WS; }
   __device__ void at_species(double *p) {
     ldj = 0;
     J = nullptr;
-    Cs = p; p += WS; gs = p; p += WS; hs = p; p += WS; iSW = p; p += WS; rW = p; p += WS;
-    cs = p; p += WS; zs = p;
+    iSW = rW = cs = nullptr;
+    Cs = p; p += WS; gs = p; p += WS; hs = p; p += WS; zs = p;
   }
 };
 
