@@ -28,6 +28,10 @@ sys.path.insert(0, ROOT)
 PEAK_ALU_TFLOPS = 78.6   # FP64 vector = non-packed FP32 vector: 256 CU x 64 FMA/clk x 2 x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
 PEAK_MFMA_F32_TFLOPS = 157.3
+# HBM bytes per launch of the mixed persistent solve kernel from rocprofv3
+# FETCH_SIZE / WRITE_SIZE passes scaled by a plain copy of known size
+# (profiles/solve_residual_53sp_pmc_traffic.md); None once that kernel changes.
+SOLVE_TRAFFIC_BYTES = 126.38e6
 EXP_FLOPS = 20.0         # an FP64 exp counted as its ~20 vector instructions
 TOL = {0: 1e-8, 1: 1e-7}
 
@@ -262,7 +266,7 @@ def main():
                    "fp64_fallbacks": st_mixed.fp64_fallbacks, "wall_ms_per_step": wall_mixed * 1e3},
         "roofline": {"kernel": "k_wpersist<64,mixed>", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
-                     "traffic": None, "kernel_ms": st_mixed.kernel_ms,
+                     "traffic": SOLVE_TRAFFIC_BYTES, "kernel_ms": st_mixed.kernel_ms,
                      "alg_flops": flops},
         "rate_kernel": rate,
         "lu_large": lu_big,
