@@ -31,7 +31,7 @@ PEAK_MFMA_F32_TFLOPS = 157.3
 # HBM bytes per launch of the mixed persistent solve kernel from rocprofv3
 # FETCH_SIZE / WRITE_SIZE passes scaled by a plain copy of known size
 # (profiles/solve_residual_53sp_pmc_traffic.md); None once that kernel changes.
-SOLVE_TRAFFIC_BYTES = 126.38e6
+SOLVE_TRAFFIC_BYTES = None
 EXP_FLOPS = 20.0         # an FP64 exp counted as its ~20 vector instructions
 TOL = {0: 1e-8, 1: 1e-7}
 
@@ -129,6 +129,35 @@ def lu_large(P, n=201, B=9830, steps=3):
             "frac_mfma_f32": tf / PEAK_MFMA_F32_TFLOPS, "nonsingular": ok}
 
 
+def uneven(P, fraction=1.0 / 64):
+    """The three-mechanism workload (30/200, 100/600, 200/1200 species /
+    reactions, 50 / 35 / 15 %) on a seeded prefix of each group, solved in one
+    mixed-precision persistent call (groups side by side on library streams)."""
+    import torch
+    from psr_inputs import uneven_workload
+    from tests.gpu_util import cond_dev, dev
+    gl, names, x0s = [], [], []
+    for name, mech, cond, x0 in uneven_workload(fraction):
+        B = x0.shape[1]
+        gl.append(dict(mech=P.Mechanism(mech), cond=cond_dev(cond), energy=True, x=dev(x0),
+                       status=torch.empty(B, dtype=torch.int32, device="cuda:0"),
+                       n_lin=torch.empty(B, dtype=torch.int32, device="cuda:0")))
+        names.append(f"{mech['species_elems'].shape[0]}/{mech['A'].shape[0]}")
+        x0s.append(dev(x0))
+    o = P.default_opts(precision=P.PSR_MIXED, scheduler=P.PSR_PERSISTENT)
+    st, ws = P.solve_batch(gl, o, stats=True)  # warm-up (same inputs)
+    for g, x0 in zip(gl, x0s):
+        g["x"].copy_(x0)
+    torch.cuda.synchronize()
+    st, _ = P.solve_batch(gl, o, workspace=ws, stats=True)
+    torch.cuda.synchronize()
+    groups = {nm: {"reactors": int(g["x"].shape[1]), "converged": int((g["status"] == 0).sum().item())}
+              for nm, g in zip(names, gl)}
+    return {"reactors": int(st.reactors), "converged": int(st.converged), "ms": st.kernel_ms,
+            "converged_per_s": st.converged / (st.kernel_ms / 1e3), "groups": groups,
+            "lin_total": int(st.lin_total), "note": f"prefix fraction {fraction:g} of each group"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +169,7 @@ def main():
                     help="reactors for the oracle baseline (0: the whole batch)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lu-large", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--rate-reactors", type=int, default=1_000_000,
                     help="batch size of the residual-kernel measurement (0: skip)")
     args = ap.parse_args()
@@ -208,6 +238,7 @@ def main():
     if args.rate_reactors > 0:
         rate = rate_kernel(P, args.rate_reactors)
     lu_big = lu_large(P) if not args.no_lu_large else None
+    unev = uneven(P) if not args.no_uneven else None
 
     # oracle on a bounded sample: CPU baseline and parity reference
     cpu = None
@@ -270,6 +301,7 @@ def main():
                      "alg_flops": flops},
         "rate_kernel": rate,
         "lu_large": lu_big,
+        "uneven": unev,
         "parity": parity,
         "cpu_baseline": cpu,
     }

@@ -151,6 +151,11 @@ typedef struct {
    * captured HIP graph on a library stream (ordered after `stream`), 0
    * launches them one by one on `stream`.  Results are identical. */
   int32_t use_graph;
+  /* mixed precision: refinement stops once the max-norm correction is below
+   * refine_tol times the max norm of the solution (default 1e-6: the Newton
+   * step needs that relative accuracy, not that of the converged state,
+   * which the FP64 step-norm and scaled-residual tests certify) */
+  double refine_tol;
 } psr_solve_opts;
 
 /* Fill opts with the defaults (FP64, plain scheduler, graph replay on,

@@ -38,7 +38,7 @@ class SolveOpts(C.Structure):
                 ("h_min", C.c_double), ("nw_h_ratio", C.c_double),
                 ("nw_max_it", C.c_int32), ("nw_every", C.c_int32), ("max_lin", C.c_int32),
                 ("max_refine", C.c_int32), ("engine", C.c_int32),
-                ("use_graph", C.c_int32)]
+                ("use_graph", C.c_int32), ("refine_tol", C.c_double)]
 
 
 class Group(C.Structure):

@@ -36,6 +36,7 @@ struct Opts {
   double rtol, atol_Y, atol_T, ftol, lambda_min, T_min, T_max;
   double ts_rtol, ts_atol_Y, ts_atol_T, ts_neg_tol, h0, h_max, h_min, nw_h_ratio;
   int nw_max_it, nw_every, max_lin, max_refine;
+  double refine_tol;
 };
 
 enum Phase : int { PH_NW_BASE = 0, PH_NW_TRIAL = 1, PH_TS1 = 2, PH_TS2 = 3, PH_DONE = 4 };

@@ -486,6 +486,7 @@ extern "C" void psr_default_opts(psr_solve_opts *o) {
   o->max_refine = 6;
   o->engine = 0;
   o->use_graph = 1;
+  o->refine_tol = 1e-6;
 }
 
 extern "C" psr_status psr_create_mechanism(const psr_mech_desc *d, psr_mech_t *out) {
@@ -795,6 +796,7 @@ static Opts to_dev_opts(const psr_solve_opts *o) {
   d.ts_neg_tol = o->ts_neg_tol; d.h0 = o->h0; d.h_max = o->h_max; d.h_min = o->h_min;
   d.nw_h_ratio = o->nw_h_ratio; d.nw_max_it = o->nw_max_it; d.nw_every = o->nw_every;
   d.max_lin = o->max_lin; d.max_refine = o->max_refine;
+  d.refine_tol = o->refine_tol;
   return d;
 }
 
@@ -994,7 +996,7 @@ static psr_status check_opts(const psr_solve_opts *o) {
       !(o->lambda_min > 0 && o->lambda_min <= 1) || !(o->T_min < o->T_max) || !(o->ts_rtol > 0) ||
       !(o->h0 > 0) || !(o->h_min > 0) || !(o->h_max > 0) || o->nw_max_it < 1 || o->nw_every < 1 ||
       o->max_lin < 1 || o->max_refine < 0 || o->engine < 0 || o->engine > 2 || o->use_graph < 0 ||
-      o->use_graph > 1)
+      o->use_graph > 1 || !(o->refine_tol > 0 && o->refine_tol < 1))
     return fail(PSR_EINVAL, "option out of range");
   return PSR_OK;
 }

@@ -119,7 +119,7 @@ __device__ inline void solve_scaled32(const Ctx &c, const float *A32, const int 
 // Solve A z = b for the current round's matrix.  FP64: z = LU64 \ b.
 // Mixed: float solve + FP64 iterative refinement against the unfactored
 // FP64 matrix (r = b - A z in FP64); refinement stops when the correction
-// is below 1e-10 of |z| in max norm; if the correction shrinks by less
+// is below refine_tol of |z| in max norm; if the correction shrinks by less
 // than half, or max_refine sweeps do not reach that, the matrix is
 // refactored in FP64 for the rest of this linearisation.
 template <int BS, bool MIXED>
@@ -157,7 +157,7 @@ __device__ void solve_round(const Ctx &c, const Opts &o, RState &s, const double
     }
     dn = block_max<BS>(dn, red);
     zn = block_max<BS>(zn, red);
-    if (dn <= 1e-10 * zn) { ok = true; break; }
+    if (dn <= o.refine_tol * zn) { ok = true; break; }
     if (!(dn <= 0.5 * prev)) break;
     prev = dn;
   }

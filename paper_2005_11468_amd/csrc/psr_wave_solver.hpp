@@ -152,7 +152,7 @@ __device__ __forceinline__ int factor32(const WCtx &c, const WArea<NP> &A, WStat
 // Solve with this round's factors.  Mixed: FP32 solve of the equilibrated
 // system plus FP64 iterative refinement against the FP64 matrix in LDS; if a
 // sweep does not halve the correction, or max_refine sweeps do not bring it
-// below 1e-10 |z|, the matrix is refactored in FP64 for the rest of this
+// below refine_tol |z|, the matrix is refactored in FP64 for the rest of this
 // linearisation.
 template <int NP, bool MIXED>
 __device__ __forceinline__ double solve_w(const WCtx &c, const WArea<NP> &A, const Opts &o, WState<NP, MIXED> &r,
@@ -174,7 +174,7 @@ __device__ __forceinline__ double solve_w(const WCtx &c, const WArea<NP> &A, con
     bool fallback = false;
     if (it > 0) {
       const double dn = wmax(in ? fabs(dz) : 0.0), zn = wmax(in ? fabs(z) : 0.0);
-      if (dn <= 1e-10 * zn) return z;
+      if (dn <= o.refine_tol * zn) return z;
       fallback = !(dn <= 0.5 * prev) || it >= o.max_refine;
       prev = dn;
     } else if (o.max_refine <= 0) {
@@ -370,7 +370,7 @@ __device__ __forceinline__ void init_w(const WCtx &c, const Opts &o, WState<NP, 
 
 __device__ __forceinline__ double inlet_enthalpy(const Tables &t, int i, double Tin) {
   const double *a = t.nasa + 7 * i;
-  const double hRT = a[0] + Tin * (a[1] / 2.0 + Tin * (a[2] / 3.0 + Tin * (a[3] / 4.0 + Tin * a[4] / 5.0)))
+  const double hRT = a[0] + Tin * (a[1] * 0.5 + Tin * (a[2] * kThird + Tin * (a[3] * 0.25 + Tin * a[4] * 0.2)))
                      + a[5] / Tin;
   return kR * Tin * hRT;
 }
