@@ -152,9 +152,11 @@ typedef struct {
    * launches them one by one on `stream`.  Results are identical. */
   int32_t use_graph;
   /* mixed precision: refinement stops once the max-norm correction is below
-   * refine_tol times the max norm of the solution (default 1e-6: the Newton
-   * step needs that relative accuracy, not that of the converged state,
-   * which the FP64 step-norm and scaled-residual tests certify) */
+   * refine_tol times the max norm of the solution (default 1e-6: enough to
+   * steer the Newton and pseudo-transient iterations).  A Newton step that
+   * passes the convergence tests is re-solved with refinement to 1e-10
+   * before it is accepted, so the converged state does not depend on
+   * refine_tol. */
   double refine_tol;
 } psr_solve_opts;
 

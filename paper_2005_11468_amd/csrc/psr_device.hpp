@@ -39,6 +39,10 @@ struct Opts {
   double refine_tol;
 };
 
+// Mixed precision: refinement target of the solve whose Newton step ends a
+// reactor's solve (the loose opts.refine_tol only steers the iteration).
+constexpr double kFinalRefine = 1e-10;
+
 enum Phase : int { PH_NW_BASE = 0, PH_NW_TRIAL = 1, PH_TS1 = 2, PH_TS2 = 3, PH_DONE = 4 };
 enum RStatus : int { RS_CONVERGED = 0, RS_MAXITER = 1, RS_TS_FAILED = 2, RS_NONFINITE = 3, RS_RUNNING = 9 };
 

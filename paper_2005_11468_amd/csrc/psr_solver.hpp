@@ -119,11 +119,11 @@ __device__ inline void solve_scaled32(const Ctx &c, const float *A32, const int 
 // Solve A z = b for the current round's matrix.  FP64: z = LU64 \ b.
 // Mixed: float solve + FP64 iterative refinement against the unfactored
 // FP64 matrix (r = b - A z in FP64); refinement stops when the correction
-// is below refine_tol of |z| in max norm; if the correction shrinks by less
+// is below tol of |z| in max norm; if the correction shrinks by less
 // than half, or max_refine sweeps do not reach that, the matrix is
 // refactored in FP64 for the rest of this linearisation.
 template <int BS, bool MIXED>
-__device__ void solve_round(const Ctx &c, const Opts &o, RState &s, const double *b, double *z) {
+__device__ void solve_round(const Ctx &c, const Opts &o, RState &s, const double *b, double *z, double tol) {
   const int n = c.n, lda = c.L.lda;
   double *red = c.p(c.L.red);
   double *A64 = c.A64();
@@ -157,7 +157,7 @@ __device__ void solve_round(const Ctx &c, const Opts &o, RState &s, const double
     }
     dn = block_max<BS>(dn, red);
     zn = block_max<BS>(zn, red);
-    if (dn <= o.refine_tol * zn) { ok = true; break; }
+    if (dn <= tol * zn) { ok = true; break; }
     if (!(dn <= 0.5 * prev)) break;
     prev = dn;
   }
@@ -268,7 +268,17 @@ __device__ void round_step(Ctx &c, const Opts &o, RState &s) {
     }
     __syncthreads();
     double *out = (ph == PH_NW_BASE || ph == PH_TS1) ? d : t;
-    solve_round<BS, MIXED>(c, o, s, G, out);
+    double tol = o.refine_tol;
+    for (;;) {
+      solve_round<BS, MIXED>(c, o, s, G, out, tol);
+      // a Newton step that would end the solve must rest on a tightly refined solve
+      if (MIXED && ph == PH_NW_BASE && !s.sing && !s.fb64 && tol > kFinalRefine && sres <= o.ftol &&
+          all_finite<BS>(out, n, red) && newton_norm<BS>(c, o, xnw, out, red) <= 1.0) {
+        tol = kFinalRefine;
+        continue;
+      }
+      break;
+    }
     if (MIXED && s.sing) {  // an FP64 refactorisation found the matrix singular
       if (ph == PH_NW_BASE) { start_ts<BS>(c, o, s); return; }
       if (ph == PH_TS1) { s.n_lin += 2; reject_ts<BS>(c, o, s, true, 0.0); return; }

@@ -152,11 +152,11 @@ __device__ __forceinline__ int factor32(const WCtx &c, const WArea<NP> &A, WStat
 // Solve with this round's factors.  Mixed: FP32 solve of the equilibrated
 // system plus FP64 iterative refinement against the FP64 matrix in LDS; if a
 // sweep does not halve the correction, or max_refine sweeps do not bring it
-// below refine_tol |z|, the matrix is refactored in FP64 for the rest of this
+// below tol |z|, the matrix is refactored in FP64 for the rest of this
 // linearisation.
 template <int NP, bool MIXED>
 __device__ __forceinline__ double solve_w(const WCtx &c, const WArea<NP> &A, const Opts &o, WState<NP, MIXED> &r,
-                          double b) {
+                          double b, double tol) {
   const int lane = lane_id(), n = c.n;
   const bool in = lane < n;
   const double *row = A.J + (in ? lane : 0) * A.ldj;
@@ -174,7 +174,7 @@ __device__ __forceinline__ double solve_w(const WCtx &c, const WArea<NP> &A, con
     bool fallback = false;
     if (it > 0) {
       const double dn = wmax(in ? fabs(dz) : 0.0), zn = wmax(in ? fabs(z) : 0.0);
-      if (dn <= o.refine_tol * zn) return z;
+      if (dn <= tol * zn) return z;
       fallback = !(dn <= 0.5 * prev) || it >= o.max_refine;
       prev = dn;
     } else if (o.max_refine <= 0) {
@@ -253,8 +253,18 @@ __device__ __forceinline__ void w_round(const WCtx &c, const WArea<NP> &A, const
     else if (ph == PH_TS2) rhs = (-G - 2.0 * r.M * r.d) / (kGamma * s.h);
     else rhs = -G;
     if (!in) rhs = 0.0;
-    double out = solve_w<NP, MIXED>(c, A, o, r, rhs);
-    if (!in) out = 0.0;
+    double out, tol = o.refine_tol;
+    for (;;) {
+      out = solve_w<NP, MIXED>(c, A, o, r, rhs, tol);
+      if (!in) out = 0.0;
+      // a Newton step that would end the solve must rest on a tightly refined solve
+      if (MIXED && ph == PH_NW_BASE && !s.sing && !s.fb64 && tol > kFinalRefine && sres <= o.ftol &&
+          !wany(in && !isfinite(out)) && newton_norm_w<NP>(c, o, r.xnw, out) <= 1.0) {
+        tol = kFinalRefine;
+        continue;
+      }
+      break;
+    }
     if (MIXED && s.sing) {
       if (ph == PH_NW_BASE) { start_ts_w(o, r); return; }
       if (ph == PH_TS1) { s.n_lin += 2; reject_ts_w(o, r, true, 0.0); return; }
