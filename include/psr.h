@@ -54,6 +54,37 @@ enum { PSR_PLAIN = 0, PSR_PERSISTENT = 1 };  /* scheduler                       
 
 typedef struct psr_mech *psr_mech_t; /* opaque; immutable after creation */
 
+/* Soot particles coupled to the gas phase (the paper's sooting reactor,
+ * Sections 1-2 and 6, modelled with Frenklach's method of moments with
+ * interpolative closure, MOMIC).  Six extra unknowns per reactor, ln M_r for
+ * r = 0..5, where M_r = sum_i m_i^r N_i per cm^3 with particle mass m in
+ * carbon atoms; only with the energy equation.  Source terms:
+ *   nucleation   I = k_n [P]^2 (mol/cm^3/s) from two molecules of the
+ *                pure-carbon precursor P; nucleus of C = 2 n_C(P) atoms;
+ *                R_r = N_A I C^r; P consumed at 2 I
+ *   growth       by the pure-carbon species G, D = n_C(G) atoms per step:
+ *                W_r = k_s [G] chi pi d^2 M_0 sum_{l<r} C(r,l) D^(r-l) mu_{l+2/3},
+ *                d = (6 m_C/(pi rho_s))^(1/3); G consumed at W_1/(D N_A)
+ *   coagulation  free-molecular, G_0 = -K_f M_0^2 f_00 / 2, G_1 = 0,
+ *                G_r = K_f M_0^2 sum_{k=1}^{r-1} C(r,k) f_{k,r-k} / 2,
+ *                K_f = 2.2 (3 m_C/(4 pi rho_s))^(1/6) (6 k_B T/rho_s)^(1/2) * coag_scale
+ * with the reduced moments mu_p = M_p/M_0 of fractional order p from the
+ * Lagrange interpolation of ln mu_l over l = 0..5 (p >= 0) or l = 0..2
+ * (p < 0), and f_{x,y} the log-Lagrange interpolation at 1/2 of the
+ * coagulation grid functions over l = 0..3.  Growth and coagulation are off
+ * while M_0 < 1 per cm^3.  Soot has zero enthalpy.  Moment rows of the
+ * residual: F_{M_r} = V (M_r/tau - R_r - W_r - G_r).                      */
+typedef struct {
+  int32_t precursor;      /* species index of P (carbon atoms only)          */
+  int32_t growth;         /* species index of G (carbon atoms only)          */
+  int32_t carbon;         /* element index of carbon                         */
+  double A_nuc, beta_nuc, E_nuc;    /* k_n = A T^beta exp(-E/RT), cm^3/(mol s), J/mol */
+  double A_grow, beta_grow, E_grow; /* k_s per surface site, same units      */
+  double site_density;    /* chi, sites per cm^2                             */
+  double soot_density;    /* rho_s, g/cm^3                                   */
+  double coag_scale;      /* factor on the coagulation kernel (1 = Frenklach's) */
+} psr_soot_desc;
+
 /* Mechanism description (host pointers, copied at creation).
  * Reactions are elementary and reversible (Eqs. 4-7): up to three distinct
  * reactant species and three distinct product species, each with a positive
@@ -71,6 +102,7 @@ typedef struct {
   const double *A;               /* [I] pre-exponential factor (Eq. 6)         */
   const double *beta;            /* [I] temperature exponent (Eq. 6)           */
   const double *Ea;              /* [I] activation energy, J/mol (Eq. 6)       */
+  const psr_soot_desc *soot;     /* NULL: gas phase only                       */
 } psr_mech_desc;
 
 /* Validate and upload a mechanism to the current device.
@@ -81,7 +113,10 @@ typedef struct {
 psr_status psr_create_mechanism(const psr_mech_desc *desc, psr_mech_t *out);
 psr_status psr_destroy_mechanism(psr_mech_t mech);
 
-/* Number of unknowns per reactor: N (isothermal) or N + 1 (energy). */
+/* Number of unknowns per reactor: N (isothermal), N + 1 (energy) or
+ * N + 7 (energy with soot: Y, T, ln M_0..ln M_5).  Soot mechanisms require
+ * energy reactors (the residual, Jacobian and solve calls return
+ * PSR_EINVAL otherwise). */
 int32_t psr_num_unknowns(psr_mech_t mech, int32_t energy);
 
 /* Reactor conditions: device pointers, [B] or [N][B]. */
@@ -158,6 +193,8 @@ typedef struct {
    * before it is accepted, so the converged state does not depend on
    * refine_tol. */
   double refine_tol;
+  /* soot: step-norm and local-error weight offsets of the ln M_r unknowns */
+  double atol_lnM, ts_atol_lnM;
 } psr_solve_opts;
 
 /* Fill opts with the defaults (FP64, plain scheduler, graph replay on,

@@ -35,6 +35,14 @@ def build(force: bool = True) -> str:
     return LIB_PATH
 
 
+class _Soot(C.Structure):
+    _fields_ = [("precursor", C.c_int), ("growth", C.c_int), ("carbon", C.c_int),
+                ("A_nuc", C.c_double), ("beta_nuc", C.c_double), ("E_nuc", C.c_double),
+                ("A_grow", C.c_double), ("beta_grow", C.c_double), ("E_grow", C.c_double),
+                ("site_density", C.c_double), ("soot_density", C.c_double),
+                ("coag_scale", C.c_double)]
+
+
 class _Mech(C.Structure):
     _fields_ = [("n_el", C.c_int), ("n_sp", C.c_int), ("n_rx", C.c_int),
                 ("elem_w", C.POINTER(C.c_double)), ("sp_el", C.POINTER(C.c_int)),
@@ -42,7 +50,8 @@ class _Mech(C.Structure):
                 ("r_idx", C.POINTER(C.c_int)), ("r_nu", C.POINTER(C.c_int)),
                 ("p_idx", C.POINTER(C.c_int)), ("p_nu", C.POINTER(C.c_int)),
                 ("A", C.POINTER(C.c_double)), ("beta", C.POINTER(C.c_double)),
-                ("Ea", C.POINTER(C.c_double)), ("W", C.POINTER(C.c_double))]
+                ("Ea", C.POINTER(C.c_double)), ("soot", C.POINTER(_Soot)),
+                ("W", C.POINTER(C.c_double))]
 
 
 class _Cond(C.Structure):
@@ -58,7 +67,8 @@ class Opts(C.Structure):
                 ("ts_neg_tol", C.c_double),
                 ("h0", C.c_double), ("h_max", C.c_double), ("h_min", C.c_double),
                 ("nw_h_ratio", C.c_double),
-                ("nw_max_it", C.c_int), ("nw_every", C.c_int), ("max_lin", C.c_int)]
+                ("nw_max_it", C.c_int), ("nw_every", C.c_int), ("max_lin", C.c_int),
+                ("atol_lnM", C.c_double), ("ts_atol_lnM", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -87,6 +97,11 @@ def lib():
         L.om_jacobian.argtypes = [mp, cp, dp, dp]
         L.om_jacobian_complex_step.argtypes = [mp, cp, dp, dp]
         L.om_mass_diag.argtypes = [mp, cp, dp, dp]
+        L.om_soot_ln_mu.argtypes = [dp, C.c_double]
+        L.om_soot_ln_mu.restype = C.c_double
+        L.om_soot_fxy.argtypes = [dp, C.c_int, C.c_int]
+        L.om_soot_fxy.restype = C.c_double
+        L.om_soot_sources.argtypes = [mp, C.c_double, C.c_double, C.c_double, dp, dp, dp, dp, dp]
         L.om_lu_factor.argtypes = [C.c_int, dp, ip]
         L.om_lu_factor.restype = C.c_int
         L.om_lu_solve.argtypes = [C.c_int, dp, ip, dp]
@@ -127,9 +142,12 @@ class Mechanism:
         self.n_rx = self._keep["r_idx"].shape[0]
         self.W = np.zeros(self.n_sp)
         k = self._keep
+        sd = mech.get("soot")
+        self.soot = None if sd is None else _Soot(*(sd[name] for name, _ in _Soot._fields_))
+        sp = C.pointer(self.soot) if self.soot is not None else C.POINTER(_Soot)()
         self.s = _Mech(self.n_el, self.n_sp, self.n_rx, _dp(k["elem_w"]), _ip(k["sp_el"]),
                        _dp(k["nasa"]), _ip(k["r_idx"]), _ip(k["r_nu"]), _ip(k["p_idx"]),
-                       _ip(k["p_nu"]), _dp(k["A"]), _dp(k["beta"]), _dp(k["Ea"]), _dp(self.W))
+                       _ip(k["p_nu"]), _dp(k["A"]), _dp(k["beta"]), _dp(k["Ea"]), sp, _dp(self.W))
         lib().om_prepare(C.byref(self.s))
 
     # -- pointwise functions ------------------------------------------------
@@ -151,7 +169,17 @@ class Mechanism:
         return Cc, q, wdot
 
     def n_unknowns(self, energy):
-        return self.n_sp + (1 if energy else 0)
+        return self.n_sp + (1 if energy else 0) + (6 if energy and self.soot is not None else 0)
+
+    # -- soot moments (MOMIC) -------------------------------------------------
+    def soot_sources(self, T, CP, CG, lnM):
+        """(R, W, G, sinks): nucleation, growth and coagulation sources of the
+        six moments, and the precursor / growth-species sinks (mol/cm^3/s)."""
+        lnM = np.ascontiguousarray(lnM, dtype=np.float64)
+        R, Wg, G, sk = np.zeros(6), np.zeros(6), np.zeros(6), np.zeros(2)
+        lib().om_soot_sources(C.byref(self.s), float(T), float(CP), float(CG), _dp(lnM), _dp(R),
+                              _dp(Wg), _dp(G), _dp(sk))
+        return R, Wg, G, sk
 
     def _cond(self, P, tau, T_in, Y_in, energy):
         Y_in = np.ascontiguousarray(Y_in, dtype=np.float64)
@@ -200,6 +228,18 @@ class Mechanism:
         lib().om_time_march_only(C.byref(self.s), C.byref(c), C.byref(opts or default_opts()),
                                  _dp(x), int(steps), C.byref(st))
         return x, st
+
+
+def soot_ln_mu(lnM, p):
+    """ln mu_p by the interpolative closure (Lagrange in ln mu over the orders)."""
+    lnM = np.ascontiguousarray(lnM, dtype=np.float64)
+    return lib().om_soot_ln_mu(_dp(lnM), float(p))
+
+
+def soot_fxy(lnM, x, y):
+    """The coagulation grid-function interpolant f_{x,y}."""
+    lnM = np.ascontiguousarray(lnM, dtype=np.float64)
+    return lib().om_soot_fxy(_dp(lnM), int(x), int(y))
 
 
 def lu_factor(a):

@@ -21,27 +21,51 @@
 #define OM_R 8.314462618       /* J/(mol K), gas constant                        */
 #define OM_PATM 101325.0       /* Pa, standard-state pressure of Eq. 8          */
 #define OM_V 1.0               /* cm^3, reactor volume (cancels from the root)   */
+#define OM_NA 6.02214076e23    /* 1/mol, Avogadro constant                       */
+#define OM_KB 1.380649e-16     /* erg/K, Boltzmann constant (cgs)                */
+#define OM_PI 3.14159265358979323846
+
+/* Lagrange basis polynomial l of the nodes 0, 1, ..., m-1, at p. */
+static double lagrange_basis(double p, int l, int m)
+{
+  double r = 1.0;
+  for (int k = 0; k < m; k++)
+    if (k != l) r *= (p - k) / (double)(l - k);
+  return r;
+}
+
+/* Binomial coefficient C(n, k). */
+static double binomial(int n, int k)
+{
+  double r = 1.0;
+  for (int i = 1; i <= k; i++) r = r * (n - k + i) / i;
+  return r;
+}
 
 /* ---- real instantiation ------------------------------------------------- */
 #define REAL double
 #define EXP_ exp
 #define LOG_ log
+#define RE_(z) (z)
 #define FN(name) name##_r
 #include "residual_body.inc"
 #undef REAL
 #undef EXP_
 #undef LOG_
+#undef RE_
 #undef FN
 
 /* ---- complex instantiation (complex-step derivative) --------------------- */
 #define REAL double complex
 #define EXP_ cexp
 #define LOG_ clog
+#define RE_(z) creal(z)
 #define FN(name) name##_c
 #include "residual_body.inc"
 #undef REAL
 #undef EXP_
 #undef LOG_
+#undef RE_
 #undef FN
 
 void om_prepare(om_mech *m)
@@ -53,7 +77,20 @@ void om_prepare(om_mech *m)
   }
 }
 
-int om_n_unknowns(const om_mech *m, int energy) { return m->n_sp + (energy ? 1 : 0); }
+int om_n_unknowns(const om_mech *m, int energy)
+{
+  return m->n_sp + (energy ? 1 : 0) + (energy && m->soot ? 6 : 0);
+}
+
+double om_soot_ln_mu(const double *lnM, double p) { return soot_ln_mu_r(lnM, p); }
+
+double om_soot_fxy(const double *lnM, int x, int y) { return soot_fxy_r(lnM, x, y); }
+
+void om_soot_sources(const om_mech *m, double T, double CP, double CG, const double *lnM,
+                     double *R, double *Wg, double *G, double *sinks)
+{
+  soot_sources_r(m, T, CP, CG, lnM, R, Wg, G, sinks);
+}
 
 void om_default_opts(om_opts *o)
 {
@@ -75,6 +112,8 @@ void om_default_opts(om_opts *o)
   o->nw_max_it = 8;
   o->nw_every = 10;
   o->max_lin = 1000;
+  o->atol_lnM = 1e-10;
+  o->ts_atol_lnM = 1e-3;
 }
 
 void om_thermo(const om_mech *m, double T, double *cp_R, double *h_RT, double *s_R)
@@ -117,13 +156,20 @@ double om_scaled_residual(const om_mech *m, const om_cond *c, const double *x)
   double *kf = malloc(sizeof(double) * NR), *kr = malloc(sizeof(double) * NR);
   double *Rf = malloc(sizeof(double) * NR), *Rr = malloc(sizeof(double) * NR);
   double *C = malloc(sizeof(double) * N), *wdot = malloc(sizeof(double) * N);
-  double *gross = calloc(N, sizeof(double)), *F = malloc(sizeof(double) * (N + 1));
+  const int n = om_n_unknowns(m, c->energy), soot = c->energy && m->soot;
+  double *gross = calloc(N, sizeof(double)), *F = malloc(sizeof(double) * n);
+  double R[6], Wg[6], G[6], sk[2] = {0.0, 0.0};
+  int Ps = -1, Gs = -1;
   double T = c->energy ? x[N] : c->T_in;
   thermo_r(m, T, NULL, h, s);
   rate_constants_r(m, T, h, s, kf, NULL, kr);
   double rho = production_r(m, T, c->P, x, kf, kr, C, Rf, Rr, NULL, wdot);
   double mdot = rho * OM_V / c->tau;
   residual_r(m, c, x, F);
+  if (soot) {
+    Ps = m->soot->precursor; Gs = m->soot->growth;
+    soot_sources_r(m, T, C[Ps], C[Gs], x + N + 1, R, Wg, G, sk);
+  }
   for (int k = 0; k < NR; k++) {
     double g = fabs(Rf[k]) + fabs(Rr[k]);
     for (int sl = 0; sl < 3; sl++) {
@@ -136,6 +182,8 @@ double om_scaled_residual(const om_mech *m, const om_cond *c, const double *x)
   double worst = 0.0;
   for (int i = 0; i < N; i++) {
     double den = mdot * (fabs(x[i]) + fabs(c->Y_in[i])) + OM_V * m->W[i] * gross[i];
+    if (i == Ps) den += OM_V * m->W[i] * sk[0];
+    if (i == Gs) den += OM_V * m->W[i] * sk[1];
     if (den > 0.0 && fabs(F[i]) / den > worst) worst = fabs(F[i]) / den;
     if (!(den >= 0.0) || F[i] != F[i]) worst = INFINITY;
   }
@@ -146,8 +194,15 @@ double om_scaled_residual(const om_mech *m, const om_cond *c, const double *x)
       double H = OM_R * T * h[i], Hin = OM_R * c->T_in * hin[i];
       den += mdot * fabs(c->Y_in[i] * (H - Hin) / m->W[i]) + OM_V * fabs(H) * gross[i];
     }
+    if (soot) den += OM_V * OM_R * T * (fabs(h[Ps]) * sk[0] + fabs(h[Gs]) * sk[1]);
     if (den > 0.0 && fabs(F[N]) / den > worst) worst = fabs(F[N]) / den;
     if (F[N] != F[N]) worst = INFINITY;
+  }
+  /* moment rows: relative to outflow plus the magnitudes of the sources */
+  for (int r = 0; soot && r < 6; r++) {
+    double den = OM_V * (exp(x[N + 1 + r]) / c->tau + fabs(R[r]) + fabs(Wg[r]) + fabs(G[r]));
+    double v = fabs(F[N + 1 + r]) / den;
+    if (!(v <= worst)) worst = v; /* a NaN wins */
   }
   free(h); free(s); free(hin); free(kf); free(kr); free(Rf); free(Rr);
   free(C); free(wdot); free(gross); free(F);
@@ -173,7 +228,8 @@ static double side_partial(double kconst, const int *idx, const int *nu, const d
  *   d ln k_r/dT = d ln k_f/dT - d ln K_c/dT                                 */
 void om_jacobian(const om_mech *m, const om_cond *c, const double *x, double *J)
 {
-  const int N = m->n_sp, NR = m->n_rx, n = N + (c->energy ? 1 : 0);
+  const int N = m->n_sp, NR = m->n_rx, n = om_n_unknowns(m, c->energy);
+  for (size_t e = 0; e < (size_t)n * n; e++) J[e] = 0.0;
   double *cp = malloc(sizeof(double) * N), *h = malloc(sizeof(double) * N);
   double *s = malloc(sizeof(double) * N), *hin = malloc(sizeof(double) * N);
   double *kf = malloc(sizeof(double) * NR), *kr = malloc(sizeof(double) * NR);
@@ -255,6 +311,19 @@ void om_jacobian(const om_mech *m, const om_cond *c, const double *x, double *J)
     for (int i = 0; i < N; i++) v += OM_V * (OM_R * cp[i] * wdot[i] + OM_R * T * h[i] * dwdT[i]);
     J[(size_t)N * n + N] = v;
   }
+  /* soot block (precursor, growth, energy and moment rows; every column):
+   * complex-step derivative of the soot terms alone, exact to rounding   */
+  if (c->energy && m->soot) {
+    double complex *xc = malloc(sizeof(double complex) * n), *Fc = malloc(sizeof(double complex) * n);
+    for (int col = 0; col < n; col++) {
+      double hstep = 1e-30 * (fabs(x[col]) > 1e-10 ? fabs(x[col]) : 1e-10);
+      for (int j = 0; j < n; j++) xc[j] = x[j];
+      xc[col] = x[col] + hstep * _Complex_I;
+      soot_only_c(m, c, xc, Fc);
+      for (int r = 0; r < n; r++) J[(size_t)r * n + col] += cimag(Fc[r]) / hstep;
+    }
+    free(xc); free(Fc);
+  }
   free(cp); free(h); free(s); free(hin); free(kf); free(kr); free(Rf); free(Rr);
   free(C); free(wdot); free(dwdY); free(dwdT); free(dqdY);
 }
@@ -277,7 +346,8 @@ void om_jacobian_complex_step(const om_mech *m, const om_cond *c, const double *
 }
 
 /* Diagonal mass matrix of the transient form of Eqs. 2-3:
- * rho V for each species row, rho V cp_mix for the energy row.              */
+ * rho V for each species row, rho V cp_mix for the energy row, V M_r for
+ * the ln M_r rows (d M_r/dt = M_r d ln M_r/dt).                             */
 void om_mass_diag(const om_mech *m, const om_cond *c, const double *x, double *M)
 {
   const int N = m->n_sp;
@@ -293,6 +363,8 @@ void om_mass_diag(const om_mech *m, const om_cond *c, const double *x, double *M
     for (int i = 0; i < N; i++) cpmix += x[i] * OM_R * cp[i] / m->W[i];
     M[N] = rho * OM_V * cpmix;
     free(cp);
+    if (m->soot)
+      for (int r = 0; r < 6; r++) M[N + 1 + r] = OM_V * exp(x[N + 1 + r]);
   }
 }
 
@@ -351,10 +423,12 @@ static int all_finite(int n, const double *v)
   return 1;
 }
 
-/* x <- x + lam * d, then Y projected onto Y >= 0 and T onto [T_min, T_max]. */
-static void step_clamped(const om_cond *c, const om_opts *o, int N, const double *x, double lam,
-                         const double *d, double *out)
+/* x <- x + lam * d, then Y projected onto Y >= 0 and T onto [T_min, T_max];
+ * ln M unbounded.                                                           */
+static void step_clamped(const om_cond *c, const om_opts *o, int N, int n, const double *x,
+                         double lam, const double *d, double *out)
 {
+  for (int i = N + 1; i < n; i++) out[i] = x[i] + lam * d[i];
   for (int i = 0; i < N; i++) {
     double v = x[i] + lam * d[i];
     out[i] = v > 0.0 ? v : 0.0;
@@ -379,13 +453,11 @@ static double bound_lambda(const om_cond *c, const om_opts *o, int N, const doub
 }
 
 /* Weighted max norm of a Newton step: max_k |d_k| / (atol_k + rtol |x_k|). */
-static double newton_norm(const om_cond *c, const om_opts *o, int N, const double *x,
-                          const double *d)
+static double newton_norm(const om_opts *o, int N, int n, const double *x, const double *d)
 {
   double r = 0.0;
-  int n = N + (c->energy ? 1 : 0);
   for (int k = 0; k < n; k++) {
-    double w = (k < N ? o->atol_Y : o->atol_T) + o->rtol * fabs(x[k]);
+    double w = (k < N ? o->atol_Y : (k == N ? o->atol_T : o->atol_lnM)) + o->rtol * fabs(x[k]);
     double t = fabs(d[k]) / w;
     if (!(t <= r)) r = t; /* a NaN wins */
   }
@@ -422,13 +494,13 @@ static int newton_attempt(const om_mech *m, const om_cond *c, const om_opts *o, 
     om_lu_solve(n, J, piv, d);
     st->n_lin++;
     if (!all_finite(n, d)) break;
-    double nd = newton_norm(c, o, N, x, d);
+    double nd = newton_norm(o, N, n, x, d);
     TRACE("NW it=%d nlin=%d nd=%.3e T=%.2f\n", it, st->n_lin, nd, c->energy ? x[N] : c->T_in);
     if (nd <= 1.0) {
       double sres = om_scaled_residual(m, c, x);
       if (sres <= o->ftol) {
         st->sres = sres;
-        step_clamped(c, o, N, x, 1.0, d, xio);
+        step_clamped(c, o, N, n, x, 1.0, d, xio);
         result = NW_CONVERGED;
         break;
       }
@@ -437,12 +509,12 @@ static int newton_attempt(const om_mech *m, const om_cond *c, const om_opts *o, 
     int accepted = 0;
     while (lam >= o->lambda_min) {
       if (st->n_lin >= o->max_lin) { result = NW_BUDGET; goto done; }
-      step_clamped(c, o, N, x, lam, d, xt);
+      step_clamped(c, o, N, n, x, lam, d, xt);
       om_residual(m, c, xt, dt);
       for (int i = 0; i < n; i++) dt[i] = -dt[i];
       om_lu_solve(n, J, piv, dt);
       st->n_lin++;
-      if (newton_norm(c, o, N, x, dt) < nd) {
+      if (newton_norm(o, N, n, x, dt) < nd) {
         memcpy(x, xt, sizeof(double) * n);
         accepted = 1;
         break;
@@ -503,7 +575,7 @@ static int ros2_step(const om_mech *m, const om_cond *c, const om_opts *o, doubl
     for (int i = 0; i < n; i++) {
       xn[i] = x[i] + 1.5 * hh * k1[i] + 0.5 * hh * k2[i];
       double ax = fabs(x[i]) > fabs(xn[i]) ? fabs(x[i]) : fabs(xn[i]);
-      double w = (i < N ? o->ts_atol_Y : o->ts_atol_T) + o->ts_rtol * ax;
+      double w = (i < N ? o->ts_atol_Y : (i == N ? o->ts_atol_T : o->ts_atol_lnM)) + o->ts_rtol * ax;
       double e = 0.5 * hh * (k1[i] + k2[i]) / w;
       s += e * e;
     }
@@ -518,7 +590,7 @@ static int ros2_step(const om_mech *m, const om_cond *c, const om_opts *o, doubl
         c->energy ? xn[N] : c->T_in, xn[0]);
   if (!bad && err <= 1.0) {
     for (int i = 0; i < N; i++) x[i] = xn[i] > 0.0 ? xn[i] : 0.0;
-    if (c->energy) x[N] = xn[N];
+    for (int i = N; i < n; i++) x[i] = xn[i];
     double fac = 0.9 / sqrt(err > 1e-10 ? err : 1e-10);
     *h = hh * (fac > 5.0 ? 5.0 : (fac < 0.2 ? 0.2 : fac));
     if (*h > o->h_max * c->tau) *h = o->h_max * c->tau;

@@ -16,7 +16,8 @@
  *   - its analytic Jacobian (the paper uses finite differences; the analytic
  *     form has the same root),
  *   - a textbook partial-pivoting LU factorisation and solve,
- *   - the hybrid damped-Newton / pseudo-transient solve of Section 3.
+ *   - the hybrid damped-Newton / pseudo-transient solve of Section 3,
+ *   - soot moments (MOMIC) coupled to the gas phase when om_mech.soot is set.
  *
  * Units: concentrations mol/cm^3, density g/cm^3, pressure Pa, energies
  * J/mol, A in (cm^3/mol)^(order-1)/s, V = 1 cm^3.
@@ -27,6 +28,22 @@
 #ifdef __cplusplus
 extern "C" {
 #endif
+
+/* Soot particle population by the method of moments with interpolative
+ * closure (MOMIC; the paper couples it to the gas phase for its sooting
+ * reactor, Sections 1-2 and 6, citing Frenklach's method).  Unknowns
+ * ln M_r, r = 0..5, with M_r = sum_i m_i^r N_i per cm^3 and m in carbon
+ * atoms.  Nucleation from two molecules of a pure-carbon precursor P,
+ * surface growth by a pure-carbon species G (n_C(G) atoms per step),
+ * free-molecular coagulation.  Soot requires the energy equation.       */
+typedef struct {
+  int precursor, growth, carbon; /* species P, species G, element index of carbon */
+  double A_nuc, beta_nuc, E_nuc;    /* k_n = A T^beta exp(-E/RT), cm^3/(mol s)   */
+  double A_grow, beta_grow, E_grow; /* k_s per surface site, cm^3/(mol s)        */
+  double site_density;              /* chi, sites per cm^2                       */
+  double soot_density;              /* rho_s, g/cm^3                             */
+  double coag_scale;                /* factor on the coagulation kernel (1 = Frenklach's) */
+} om_soot;
 
 typedef struct {
   int n_el, n_sp, n_rx;
@@ -40,6 +57,7 @@ typedef struct {
   const double *A;       /* [I]                                      */
   const double *beta;    /* [I]                                      */
   const double *Ea;      /* [I] J/mol                                */
+  const om_soot *soot;   /* NULL: gas phase only                     */
   double *W;             /* [N] work: species weights, filled by om_prepare */
 } om_mech;
 
@@ -66,6 +84,8 @@ typedef struct {
   int nw_max_it;               /* iterations per Newton attempt                */
   int nw_every;                /* accepted steps between Newton attempts       */
   int max_lin;                 /* total linear-solve budget                    */
+  double atol_lnM;             /* step-norm weight offset of the ln M_r unknowns */
+  double ts_atol_lnM;          /* local-error weight offset of the ln M_r unknowns */
 } om_opts;
 
 enum { OM_CONVERGED = 0, OM_MAXITER = 1, OM_TS_FAILED = 2, OM_NONFINITE = 3 };
@@ -92,6 +112,12 @@ double om_scaled_residual(const om_mech *m, const om_cond *c, const double *x);
 void om_jacobian(const om_mech *m, const om_cond *c, const double *x, double *J);
 void om_jacobian_complex_step(const om_mech *m, const om_cond *c, const double *x, double *J);
 void om_mass_diag(const om_mech *m, const om_cond *c, const double *x, double *M);
+
+/* MOMIC pieces, exported for the tests.  lnM: [6] ln M_r.               */
+double om_soot_ln_mu(const double *lnM, double p);
+double om_soot_fxy(const double *lnM, int x, int y);
+void om_soot_sources(const om_mech *m, double T, double CP, double CG, const double *lnM,
+                     double *R, double *Wg, double *G, double *sinks);
 
 int om_lu_factor(int n, double *a, int *piv);
 void om_lu_solve(int n, const double *lu, const int *piv, double *b);

@@ -58,10 +58,13 @@ class Mechanism:
         self.n_reactions = a["ri"].shape[0]
         dpp = lambda x: x.ctypes.data_as(_lib.dp)
         ipp = lambda x: x.ctypes.data_as(_lib.ip)
+        sd = mech.get("soot")
+        self._soot = None if sd is None else _lib.SootDesc(*(sd[k] for k, _ in _lib.SootDesc._fields_))
+        sp = C.pointer(self._soot) if self._soot is not None else C.POINTER(_lib.SootDesc)()
         desc = _lib.MechDesc(a["se"].shape[1], self.n_species, self.n_reactions, dpp(a["ew"]),
                              ipp(a["se"]), dpp(a["nasa"]), float(mech.get("t_low", 300.0)),
                              float(mech.get("t_high", 3000.0)), ipp(a["ri"]), ipp(a["rn"]),
-                             ipp(a["pi"]), ipp(a["pn"]), dpp(a["A"]), dpp(a["beta"]), dpp(a["Ea"]))
+                             ipp(a["pi"]), ipp(a["pn"]), dpp(a["A"]), dpp(a["beta"]), dpp(a["Ea"]), sp)
         h = C.c_void_p()
         _lib.check(L.psr_create_mechanism(C.byref(desc), C.byref(h)), "psr_create_mechanism")
         self.handle = h
@@ -75,6 +78,14 @@ class Mechanism:
         if h is not None and lib is not None:
             lib.psr_destroy_mechanism(h)
             self.handle = None
+
+
+def _check_state(mech: Mechanism, energy: bool, x, B: int, name: str = "x"):
+    """x must be [n][B] with n the mechanism's unknown count (the library reads
+    n rows of B values)."""
+    n = mech.n_unknowns(energy)
+    if tuple(x.shape) != (n, B):
+        raise ValueError(f"{name} must have shape ({n}, {B}), got {tuple(x.shape)}")
 
 
 def _conditions(cond: dict, energy: bool):
@@ -93,8 +104,10 @@ def residual(mech: Mechanism, cond: dict, energy: bool, x, F=None, scaled=None, 
     torch = _torch()
     c = _conditions(cond, energy)
     x = _dev_f64(x, "x")
+    _check_state(mech, energy, x, c.n_reactors)
     if F is None:
         F = torch.empty_like(x)
+    _check_state(mech, energy, _dev_f64(F, "F"), c.n_reactors, "F")
     st = _lib.load().psr_residual(mech.handle, C.byref(c), _ptr(x), _ptr(F),
                                   _ptr(scaled) if scaled is not None else None, _stream(stream))
     _lib.check(st, "psr_residual")
@@ -106,6 +119,7 @@ def jacobian(mech: Mechanism, cond: dict, energy: bool, x, J=None, stream=None):
     torch = _torch()
     c = _conditions(cond, energy)
     x = _dev_f64(x, "x")
+    _check_state(mech, energy, x, c.n_reactors)
     n, B = x.shape
     if J is None:
         J = torch.empty((B, n, n), dtype=torch.float64, device=x.device)
@@ -153,6 +167,7 @@ class _Groups:
         for i, g in enumerate(groups):
             c = _conditions(g["cond"], g["energy"])
             x = _dev_f64(g["x"], "x")
+            _check_state(g["mech"], g["energy"], x, c.n_reactors)
             st = g["status"]
             nl = g.get("n_lin")
             arr[i] = _lib.Group(g["mech"].handle, c, _ptr(x), _ptr(st),

@@ -15,12 +15,20 @@ STATUS_NAMES = {0: "CONVERGED", 1: "MAXITER", 2: "TS_FAILED", 3: "NONFINITE"}
 dp, ip, vp = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_void_p
 
 
+class SootDesc(C.Structure):
+    _fields_ = [("precursor", C.c_int32), ("growth", C.c_int32), ("carbon", C.c_int32),
+                ("A_nuc", C.c_double), ("beta_nuc", C.c_double), ("E_nuc", C.c_double),
+                ("A_grow", C.c_double), ("beta_grow", C.c_double), ("E_grow", C.c_double),
+                ("site_density", C.c_double), ("soot_density", C.c_double),
+                ("coag_scale", C.c_double)]
+
+
 class MechDesc(C.Structure):
     _fields_ = [("n_elements", C.c_int32), ("n_species", C.c_int32), ("n_reactions", C.c_int32),
                 ("elem_weight", dp), ("species_elems", ip), ("nasa7", dp),
                 ("t_low", C.c_double), ("t_high", C.c_double),
                 ("reac_idx", ip), ("reac_nu", ip), ("prod_idx", ip), ("prod_nu", ip),
-                ("A", dp), ("beta", dp), ("Ea", dp)]
+                ("A", dp), ("beta", dp), ("Ea", dp), ("soot", C.POINTER(SootDesc))]
 
 
 class Conditions(C.Structure):
@@ -38,7 +46,8 @@ class SolveOpts(C.Structure):
                 ("h_min", C.c_double), ("nw_h_ratio", C.c_double),
                 ("nw_max_it", C.c_int32), ("nw_every", C.c_int32), ("max_lin", C.c_int32),
                 ("max_refine", C.c_int32), ("engine", C.c_int32),
-                ("use_graph", C.c_int32), ("refine_tol", C.c_double)]
+                ("use_graph", C.c_int32), ("refine_tol", C.c_double),
+                ("atol_lnM", C.c_double), ("ts_atol_lnM", C.c_double)]
 
 
 class Group(C.Structure):

@@ -29,7 +29,26 @@ struct MechDev {
   const int *r_idx, *r_nu, *p_idx, *p_nu;  // [I*3], -1 pads
   const int *sp_ptr, *sp_rx, *sp_nu;       // species -> (reaction, net nu), CSR
   const int *packed;  // wavefront engine: w0[I], w1[I], w2[I], CSR entries[nnz]; null if unusable
+  // soot moments (MOMIC); soot == 0: gas phase only
+  int soot, sP, sG;                 // precursor and growth species
+  double Cmin, D;                   // carbon atoms per nucleus and per growth step
+  double An, bn, EnR, As, bs, EsR;  // k_n, k_s = A T^b exp(-(E/R)/T), E/R in K
+  double KW;                        // chi pi d^2 (d: diameter of one carbon atom's soot volume)
+  double KF0;                       // free-molecular coagulation kernel / sqrt(T)
+  const double *frac;               // [kSootOrders][6] d ln mu_p / d ln M_j, then [4] L_l(1/2)
 };
+
+// Unknowns per reactor: Y[, T][, ln M_0..ln M_5].
+__host__ __device__ inline int n_unknowns(const MechDev &m, int energy) {
+  return m.N + (energy ? 1 + (m.soot ? 6 : 0) : 0);
+}
+
+// Fractional orders of the soot closure: index 3 j + t is order j + 1/6
+// (t = 0), j - 1/6 (t = 1), j - 1/2 (t = 2) for j = 0..7 (coagulation); 24 + l
+// is order l + 2/3 for l = 0..4 (surface growth).
+constexpr int kSootOrders = 29;
+constexpr int kSootPairs = 11;  // (x, y) of the coagulation interpolants f_{x,y}
+constexpr int kSootScratch = 7 * (kSootOrders + 4 * kSootPairs + kSootPairs) + 12 * 6 + 16;
 
 struct Opts {
   int precision, scheduler;
@@ -37,6 +56,7 @@ struct Opts {
   double ts_rtol, ts_atol_Y, ts_atol_T, ts_neg_tol, h0, h_max, h_min, nw_h_ratio;
   int nw_max_it, nw_every, max_lin, max_refine;
   double refine_tol;
+  double atol_lnM, ts_atol_lnM;  // soot moments
 };
 
 // Mixed precision: refinement target of the solve whose Newton step ends a
@@ -67,6 +87,7 @@ struct Layout {
   int split, mat_total;  // split: matrices in a separate (HBM) area of mat_total doubles
   int C, hRT, sR, cpR, wdot, gross, Erow, dwdT;       // species scratch
   int kf, kr, Rf, Rr, sumC, dqdT, dqdC;               // reaction scratch
+  int soot;                                           // soot-closure scratch (n = N + 7 only)
   int red, total;
   __host__ __device__ void make(int N_, int I_, int n_, bool mixed, int BS, bool split_ = false) {
     N = N_; I = I_; n = n_;
@@ -87,6 +108,7 @@ struct Layout {
     gross = o; o += N; Erow = o; o += N; dwdT = o; o += N;
     kf = o; o += I; kr = o; o += I; Rf = o; o += I; Rr = o; o += I;
     sumC = o; o += I; dqdT = o; o += I; dqdC = o; o += 6 * I;
+    soot = o; o += (n == N + 7) ? kSootScratch : 0;
     red = o; o += BS + 8;
     total = o;
   }
@@ -158,6 +180,150 @@ __device__ void load_inlet(Ctx &c, const double *Yin_soa, int64_t B, int64_t b) 
   }
 }
 
+// ------------------------------------------------------------- soot (MOMIC)
+//
+// Frenklach's method of moments with interpolative closure for the soot
+// particles of a sooting reactor (the paper couples it to the gas phase,
+// Sections 1-2 and 6).  The closure needs reduced moments mu_p = M_p/M_0 of
+// fractional order p; ln mu_p is a fixed linear combination of the ln M_j
+// (Lagrange interpolation over the integer orders, coefficients tabulated
+// at mechanism creation), so every quantity below carries its value and its
+// six derivatives with respect to ln M_0..ln M_5 (index 0 and 1..6 of a
+// 7-double record).  Stages run on a few threads each, separated by block
+// barriers; all threads of the workgroup must call soot_eval.
+
+namespace soot {
+constexpr double kNA = 6.02214076e23;  // 1/mol
+constexpr int MU = 0, FL = MU + 7 * kSootOrders, FX = FL + 7 * 4 * kSootPairs;
+constexpr int OUT = FX + 7 * kSootPairs;  // per r: R, W, G, dsrc/dlnM[6], dsrc/dCP, dsrc/dCG, dsrc/dT|C
+constexpr int W1 = OUT + 12 * 6;           // W_1, dW_1/dlnM[6], dW_1/dCG, dW_1/dT|C
+constexpr int SK = W1 + 9;                 // s_P = 2 I, ds_P/dCP, ds_P/dT|C
+static_assert(SK + 3 <= kSootScratch, "soot scratch");
+// coagulation pairs (x, y): (0,0), then x + y = 2, 3, 4, 5 with x = 1..r-1
+__device__ constexpr int kPairX[kSootPairs] = {0, 1, 1, 2, 1, 2, 3, 1, 2, 3, 4};
+__device__ constexpr int kPairY[kSootPairs] = {0, 1, 2, 1, 3, 2, 1, 4, 3, 2, 1};
+__device__ constexpr int kPairBase[6] = {0, 0, 1, 2, 4, 7};  // first pair with x + y = r
+__device__ constexpr double kBinom[6][6] = {{1, 0, 0, 0, 0, 0}, {1, 1, 0, 0, 0, 0}, {1, 2, 1, 0, 0, 0},
+                                            {1, 3, 3, 1, 0, 0}, {1, 4, 6, 4, 1, 0}, {1, 5, 10, 10, 5, 1}};
+}  // namespace soot
+
+// Sources of the six moments and the gas sinks at (T, CP, CG, ln M), with
+// derivatives (results in the OUT / W1 / SK records of `w`):
+//   R_r = N_A k_n CP^2 Cmin^r                      nucleation
+//   W_r = k_s CG chi pi d^2 M_0 sum_{l<r} C(r,l) D^(r-l) mu_{l+2/3}   growth
+//   G_0 = -K_f M_0^2 f_00 / 2, G_1 = 0, G_r = K_f M_0^2 sum_k C(r,k) f_{k,r-k} / 2
+// Growth and coagulation are off while M_0 < 1 per cm^3.
+template <int BS>
+__device__ void soot_eval(const MechDev &m, double T, double CP, double CG, const double *lnM, double *w) {
+  const int t = threadIdx.x;
+  if (t < kSootOrders) {  // fractional moments
+    const double *cf = m.frac + 6 * t;
+    double l = 0.0;
+    for (int j = 0; j < 6; j++) l += cf[j] * lnM[j];
+    const double mu = exp(l);
+    double *o = w + soot::MU + 7 * t;
+    o[0] = mu;
+    for (int j = 0; j < 6; j++) o[1 + j] = mu * cf[j];
+  }
+  __syncthreads();
+  if (t < 4 * kSootPairs) {  // coagulation grid functions f_l of pair q
+    const int q = t >> 2, l = t & 3, x = soot::kPairX[q], y = soot::kPairY[q];
+    double f[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k <= l; k++) {
+      const double b = soot::kBinom[l][k];
+      const double *a0 = w + soot::MU + 7 * (3 * (k + x) + 0), *a1 = w + soot::MU + 7 * (3 * (k + x) + 1);
+      const double *a2 = w + soot::MU + 7 * (3 * (k + x) + 2);
+      const int jb = l - k + y;
+      const double *b0 = w + soot::MU + 7 * (3 * jb + 0), *b1 = w + soot::MU + 7 * (3 * jb + 1);
+      const double *b2 = w + soot::MU + 7 * (3 * jb + 2);
+      // mu_{j+1/6} mu_{j'-1/2} + 2 mu_{j-1/6} mu_{j'-1/6} + mu_{j-1/2} mu_{j'+1/6}
+      f[0] += b * (a0[0] * b2[0] + 2.0 * a1[0] * b1[0] + a2[0] * b0[0]);
+      for (int j = 1; j < 7; j++)
+        f[j] += b * (a0[j] * b2[0] + a0[0] * b2[j] + 2.0 * (a1[j] * b1[0] + a1[0] * b1[j]) +
+                     a2[j] * b0[0] + a2[0] * b0[j]);
+    }
+    double *o = w + soot::FL + 7 * t;
+    for (int j = 0; j < 7; j++) o[j] = f[j];
+  }
+  __syncthreads();
+  if (t < kSootPairs) {  // f_{x,y}: log-Lagrange value at l = 1/2
+    const double *L4 = m.frac + 6 * kSootOrders;
+    const double *fl = w + soot::FL + 7 * 4 * t;
+    double lf = 0.0, d[6] = {0, 0, 0, 0, 0, 0};
+    for (int l = 0; l < 4; l++) {
+      lf += L4[l] * log(fl[7 * l]);
+      const double inv = L4[l] / fl[7 * l];
+      for (int j = 0; j < 6; j++) d[j] += inv * fl[7 * l + 1 + j];
+    }
+    const double v = exp(lf);
+    double *o = w + soot::FX + 7 * t;
+    o[0] = v;
+    for (int j = 0; j < 6; j++) o[1 + j] = v * d[j];
+  }
+  __syncthreads();
+  if (t < 7) {
+    const double lnT = log(T), invT = 1.0 / T;
+    const double kn = m.An * exp(m.bn * lnT - m.EnR * invT), dlkn = (m.bn + m.EnR * invT) * invT;
+    const double ks = m.As * exp(m.bs * lnT - m.EsR * invT), dlks = (m.bs + m.EsR * invT) * invT;
+    if (t == 6) {
+      w[soot::SK] = 2.0 * kn * CP * CP;
+      w[soot::SK + 1] = 4.0 * kn * CP;
+      w[soot::SK + 2] = 2.0 * kn * CP * CP * dlkn;
+    } else {
+      const int r = t;
+      double cr = 1.0;
+      for (int i = 0; i < r; i++) cr *= m.Cmin;
+      const double Rv = soot::kNA * kn * CP * CP * cr;
+      const double M0 = exp(lnM[0]);
+      const bool on = M0 >= 1.0;
+      // growth
+      double S = 0.0, dS[6] = {0, 0, 0, 0, 0, 0};
+      for (int l = 0; l < r; l++) {
+        double dp = 1.0;
+        for (int i = 0; i < r - l; i++) dp *= m.D;
+        const double cw = soot::kBinom[r][l] * dp;
+        const double *mu = w + soot::MU + 7 * (24 + l);
+        S += cw * mu[0];
+        for (int j = 0; j < 6; j++) dS[j] += cw * mu[1 + j];
+      }
+      const double kw = on ? m.KW * ks * M0 : 0.0;
+      const double Wv = kw * CG * S;
+      double dW[6];
+      for (int j = 0; j < 6; j++) dW[j] = kw * CG * (dS[j] + (j == 0 ? S : 0.0));
+      // coagulation
+      double Gs = 0.0, dG[6] = {0, 0, 0, 0, 0, 0};
+      if (r == 0) {
+        const double *f = w + soot::FX;
+        Gs = -0.5 * f[0];
+        for (int j = 0; j < 6; j++) dG[j] = -0.5 * f[1 + j];
+      } else if (r >= 2) {
+        for (int k = 1; k < r; k++) {
+          const double *f = w + soot::FX + 7 * (soot::kPairBase[r] + k - 1);
+          const double cb = 0.5 * soot::kBinom[r][k];
+          Gs += cb * f[0];
+          for (int j = 0; j < 6; j++) dG[j] += cb * f[1 + j];
+        }
+      }
+      const double kg = on ? m.KF0 * sqrt(T) * M0 * M0 : 0.0;
+      const double Gv = kg * Gs;
+      double *o = w + soot::OUT + 12 * r;
+      o[0] = Rv; o[1] = Wv; o[2] = Gv;
+      for (int j = 0; j < 6; j++) o[3 + j] = dW[j] + kg * (dG[j] + (j == 0 ? 2.0 * Gs : 0.0));
+      o[9] = 2.0 * soot::kNA * kn * CP * cr;
+      o[10] = kw * S;
+      o[11] = Rv * dlkn + Wv * dlks + 0.5 * Gv * invT;
+      if (r == 1) {
+        double *q = w + soot::W1;
+        q[0] = Wv;
+        for (int j = 0; j < 6; j++) q[1 + j] = dW[j];
+        q[7] = kw * S;
+        q[8] = Wv * dlks;
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // Steady residual F(x) (Eq. 2 and Eq. 3 times -rho V) with the rates of
 // Eqs. 4-9.  Leaves C, thermo, k_f, k_r, forward/reverse terms and wdot in
 // the context for the Jacobian.  Returns the scaled residual if asked for
@@ -216,6 +382,17 @@ __device__ double residual(Ctx &c, const double *x, double *F, bool want_sres) {
     Rf[k] = fwd; Rr[k] = rev;
   }
   __syncthreads();
+  // soot moments: sources and the precursor / growth-species sinks
+  const bool soot = m.soot && c.energy;
+  double *sw = soot ? c.p(c.L.soot) : nullptr;
+  if (soot) soot_eval<BS>(m, T, C[m.sP], C[m.sG], x + N + 1, sw);
+  // molar consumption rate of species i by soot formation
+  auto sink = [&](int i) -> double {
+    if (!soot) return 0.0;
+    if (i == m.sP) return sw[soot::SK];
+    if (i == m.sG) return sw[soot::W1] / (m.D * soot::kNA);
+    return 0.0;
+  };
   // species: Eq. 4 and the species residual
   double inflow = 0.0, chem = 0.0, sr = 0.0;
   for (int i = tid; i < N; i += BS) {
@@ -227,15 +404,16 @@ __device__ double residual(Ctx &c, const double *x, double *F, bool want_sres) {
     }
     wdot[i] = w;
     gross[i] = gr;
-    const double Fi = mdot * (x[i] - Yin[i]) - kV * m.W[i] * w;
+    const double sk = sink(i);
+    const double Fi = mdot * (x[i] - Yin[i]) - kV * m.W[i] * (w - sk);
     F[i] = Fi;
     if (c.energy) {
       const double H = kR * T * hRT[i];
       inflow += Yin[i] * (H - Hin[i]) / m.W[i];
-      chem += H * w;
+      chem += H * (w - sk);
     }
     if (want_sres) {
-      const double den = mdot * (fabs(x[i]) + fabs(Yin[i])) + kV * m.W[i] * gr;
+      const double den = mdot * (fabs(x[i]) + fabs(Yin[i])) + kV * m.W[i] * (gr + sk);
       double r = (den > 0.0) ? fabs(Fi) / den : 0.0;
       if (!(den >= 0.0) || Fi != Fi) r = __builtin_inf();
       sr = fmax(sr, r);
@@ -254,7 +432,7 @@ __device__ double residual(Ctx &c, const double *x, double *F, bool want_sres) {
       double den = 0.0;
       for (int i = tid; i < N; i += BS) {
         const double H = kR * T * hRT[i];
-        den += mdot * fabs(Yin[i] * (H - Hin[i]) / m.W[i]) + kV * fabs(H) * gross[i];
+        den += mdot * fabs(Yin[i] * (H - Hin[i]) / m.W[i]) + kV * fabs(H) * (gross[i] + sink(i));
       }
       den = block_sum<BS>(den, red);
       if (tid == 0) {
@@ -263,8 +441,22 @@ __device__ double residual(Ctx &c, const double *x, double *F, bool want_sres) {
         sr = fmax(sr, r);
       }
     }
-    sres = block_max<BS>(sr, red);
   }
+  // moment rows: V (M_r/tau - R_r - W_r - G_r), relative to outflow plus
+  // the magnitudes of the sources
+  if (soot && tid < 6) {
+    const double *o = sw + soot::OUT + 12 * tid;
+    const double Mr = exp(x[N + 1 + tid]);
+    const double Fr = kV * (Mr / c.tau - (o[0] + o[1] + o[2]));
+    F[N + 1 + tid] = Fr;
+    if (want_sres) {
+      const double den = kV * (Mr / c.tau + fabs(o[0]) + fabs(o[1]) + fabs(o[2]));
+      double r = fabs(Fr) / den;
+      if (!(r == r)) r = __builtin_inf();
+      sr = fmax(sr, r);
+    }
+  }
+  if (want_sres) sres = block_max<BS>(sr, red);
   __syncthreads();
   return sres;
 }
@@ -282,6 +474,61 @@ __device__ void mass_diag(Ctx &c, const double *x, double *M) {
   const double cpmix = c.energy ? block_sum<BS>(cp, red) : 0.0;
   for (int i = tid; i < N; i += BS) M[i] = c.rho * kV;
   if (c.energy && tid == 0) M[N] = c.rho * kV * cpmix;
+  // soot: d M_r/dt = M_r d ln M_r/dt
+  if (c.energy && c.m.soot && tid < 6) M[N + 1 + tid] = kV * exp(x[N + 1 + tid]);
+  __syncthreads();
+}
+
+// Soot terms of the Jacobian, added to A after the gas-phase part: rows of
+// the precursor, the growth species, the energy equation and the moments.
+// The concentrations depend on every Y and on T through rho:
+//   dC_j/dY_m = rho delta_jm / W_j - C_j/(S W_m),  dC_j/dT = -C_j/T.
+// Uses the soot records of the residual() call at the same x.
+template <int BS>
+__device__ void soot_jacobian(Ctx &c, const double *x, double *A, int lda) {
+  const MechDev &m = c.m;
+  const int N = c.N, tid = threadIdx.x, P = m.sP, Gs = m.sG;
+  const double *C = c.p(c.L.C), *hRT = c.p(c.L.hRT), *cpR = c.p(c.L.cpR);
+  const double *w = c.p(c.L.soot);
+  const double T = c.T, S = c.S, rho = c.rho, invT = 1.0 / T;
+  const double gD = 1.0 / (m.D * soot::kNA);  // mol of G per carbon atom of growth
+  const double HP = kR * T * hRT[P], HG = kR * T * hRT[Gs];
+  const double *sk = w + soot::SK, *w1 = w + soot::W1;
+  for (int mm = tid; mm < N; mm += BS) {  // species columns
+    const double SW = S * m.W[mm];
+    const double dCP = (mm == P ? rho / m.W[P] : 0.0) - C[P] / SW;
+    const double dCG = (mm == Gs ? rho / m.W[Gs] : 0.0) - C[Gs] / SW;
+    const double dsP = sk[1] * dCP, dsG = w1[7] * dCG * gD;
+    A[(int64_t)P * lda + mm] += kV * m.W[P] * dsP;
+    A[(int64_t)Gs * lda + mm] += kV * m.W[Gs] * dsG;
+    A[(int64_t)N * lda + mm] -= kV * (HP * dsP + HG * dsG);
+    for (int r = 0; r < 6; r++) {
+      const double *o = w + soot::OUT + 12 * r;
+      A[(int64_t)(N + 1 + r) * lda + mm] -= kV * (o[9] * dCP + o[10] * dCG);
+    }
+  }
+  if (tid >= BS - 7) {  // temperature and ln M columns, one per thread
+    const int col = N + (tid - (BS - 7));
+    if (col == N) {
+      const double dCP = -C[P] * invT, dCG = -C[Gs] * invT;
+      const double dsP = sk[2] + sk[1] * dCP, dsG = (w1[8] + w1[7] * dCG) * gD;
+      A[(int64_t)P * lda + N] += kV * m.W[P] * dsP;
+      A[(int64_t)Gs * lda + N] += kV * m.W[Gs] * dsG;
+      A[(int64_t)N * lda + N] -= kV * (kR * cpR[P] * sk[0] + HP * dsP + kR * cpR[Gs] * w1[0] * gD + HG * dsG);
+      for (int r = 0; r < 6; r++) {
+        const double *o = w + soot::OUT + 12 * r;
+        A[(int64_t)(N + 1 + r) * lda + N] -= kV * (o[11] + o[9] * dCP + o[10] * dCG);
+      }
+    } else {
+      const int j = col - N - 1;
+      A[(int64_t)Gs * lda + col] += kV * m.W[Gs] * w1[1 + j] * gD;
+      A[(int64_t)N * lda + col] -= kV * HG * w1[1 + j] * gD;
+      for (int r = 0; r < 6; r++) {
+        const double *o = w + soot::OUT + 12 * r;
+        A[(int64_t)(N + 1 + r) * lda + col] += kV * ((r == j ? exp(x[N + 1 + r]) / c.tau : 0.0) - o[3 + j]);
+      }
+    }
+  }
   __syncthreads();
 }
 
@@ -399,6 +646,7 @@ __device__ void jacobian(Ctx &c, const double *x, double *A, int lda) {
     if (c.energy) row[N] = -mdot * invT * yd - kV * Wi * dwdT[i];
   }
   __syncthreads();
+  if (c.energy && m.soot) soot_jacobian<BS>(c, x, A, lda);
 }
 
 // ------------------------------------------------------------- dense LU

@@ -67,7 +67,7 @@ __device__ inline Ctx make_ctx(const MechDev &m, const Layout &L, int energy, do
   Ctx c;
   c.m = m;
   c.N = m.N;
-  c.n = m.N + (energy ? 1 : 0);
+  c.n = n_unknowns(m, energy);
   c.energy = energy;
   c.P = P;
   c.tau = tau;
@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(kBS) k_residual(MechDev m, int energy, int64_t
   extern __shared__ double lds[];
   const int64_t b = blockIdx.x;
   Layout L;
-  L.make(m.N, m.I, m.N + (energy ? 1 : 0), false, kBS, true);  // no matrix needed
+  L.make(m.N, m.I, n_unknowns(m, energy), false, kBS, true);  // no matrix needed
   Ctx c = make_ctx(m, L, energy, P[b], tau[b], Tin[b], lds);
   load_inlet<kBS>(c, Yin, B, b);
   double *xl = c.p(L.x), *G = c.p(L.G);
@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(kBS) k_jacobian(MechDev m, int energy, int64_t
   extern __shared__ double lds[];
   const int64_t b = blockIdx.x;
   Layout L;
-  L.make(m.N, m.I, m.N + (energy ? 1 : 0), false, kBS, true);  // the matrix is the output
+  L.make(m.N, m.I, n_unknowns(m, energy), false, kBS, true);  // the matrix is the output
   Ctx c = make_ctx(m, L, energy, P[b], tau[b], Tin[b], lds);
   load_inlet<kBS>(c, Yin, B, b);
   double *xl = c.p(L.x), *G = c.p(L.G);
@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(kBS) k_round(GroupDev g, Opts o, RState *state
   RState s = states[b];
   if (!FIRST && s.phase == PH_DONE) return;
   Layout L;
-  L.make(g.m.N, g.m.I, g.m.N + (g.energy ? 1 : 0), MIXED, kBS, split != 0);
+  L.make(g.m.N, g.m.I, n_unknowns(g.m, g.energy), MIXED, kBS, split != 0);
   Ctx c = make_ctx(g.m, L, g.energy, g.P[b], g.tau[b], g.Tin[b], lds);
   const int persist = L.persist;
   double *mine = area + b * (int64_t)(L.persist + L.mat_total);
@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(kBS) k_persistent(GroupDev g, Opts o, RState *
                                                     double *matws) {
   extern __shared__ double lds[];
   Layout L;
-  L.make(g.m.N, g.m.I, g.m.N + (g.energy ? 1 : 0), MIXED, kBS, matws != nullptr);
+  L.make(g.m.N, g.m.I, n_unknowns(g.m, g.energy), MIXED, kBS, matws != nullptr);
   int *next = reinterpret_cast<int *>(lds + L.red + kBS + 4);
   for (;;) {
     if (threadIdx.x == 0) *next = atomicAdd(queue, 1);
@@ -288,7 +288,7 @@ __device__ inline void make_wctx(WCtx &c, const Tables &t, const GroupDev &g, in
   const int lane = lane_id();
   c.t = t;
   c.N = g.m.N;
-  c.n = g.m.N + (g.energy ? 1 : 0);
+  c.n = n_unknowns(g.m, g.energy);
   c.energy = g.energy;
   c.P = g.P[b];
   c.tau = g.tau[b];
@@ -321,7 +321,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
   if (threadIdx.x == 0) *ol = og;
   __syncthreads();
   const Opts &o = *ol;
-  const int n = g.m.N + (g.energy ? 1 : 0);
+  const int n = n_unknowns(g.m, g.energy);
   const size_t toff = wave_area_off(g.m.N, g.m.I, g.m.nnz);
   WArea<NP> A;
   A.at(reinterpret_cast<double *>(base + toff) + (size_t)wave_id() * WArea<NP>::doubles(n), n);
@@ -396,7 +396,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
   if (threadIdx.x == 0) *ol = og;
   __syncthreads();
   const Opts &o = *ol;
-  const int n = g.m.N + (g.energy ? 1 : 0);
+  const int n = n_unknowns(g.m, g.energy);
   const int64_t b = (int64_t)blockIdx.x * rpw + wave_id();
   if (b >= g.B) return;
   RState s0 = states[b];
@@ -438,7 +438,7 @@ k_wresidual(GroupDev g, double *F, double *scaled) {
   char *base = reinterpret_cast<char *>(lds);
   const Tables t = stage_tables(g.m, base, g.m.packed);
   __syncthreads();
-  const int n = g.m.N + (g.energy ? 1 : 0);
+  const int n = n_unknowns(g.m, g.energy);
   const size_t toff = align16(tables_bytes(g.m.N, g.m.I, g.m.nnz));
   WArea<64> A;
   A.at_species(reinterpret_cast<double *>(base + toff) + (size_t)wave_id() * WArea<64>::species_doubles());
@@ -487,6 +487,56 @@ extern "C" void psr_default_opts(psr_solve_opts *o) {
   o->engine = 0;
   o->use_graph = 1;
   o->refine_tol = 1e-6;
+  o->atol_lnM = 1e-10;
+  o->ts_atol_lnM = 1e-3;
+}
+
+// Lagrange basis polynomial l over the nodes 0..m-1, at p.
+static double lagrange(double p, int l, int m) {
+  double v = 1.0;
+  for (int k = 0; k < m; k++)
+    if (k != l) v *= (p - k) / (double)(l - k);
+  return v;
+}
+
+// Validate a soot description and build the closure table: for each
+// fractional order p of the closure (index order of kSootOrders), the
+// coefficients c_j of ln mu_p = sum_j c_j ln M_j, from the Lagrange
+// interpolation of ln mu_l = ln M_l - ln M_0 over l = 0..5 (p >= 0) or
+// l = 0..2 (p < 0); then the four weights L_l(1/2), l = 0..3.
+static psr_status soot_tables(const psr_mech_desc *d, std::vector<double> &frac) {
+  const psr_soot_desc *sd = d->soot;
+  const int E = d->n_elements, N = d->n_species;
+  if (sd->carbon < 0 || sd->carbon >= E) return fail(PSR_EINVAL, "soot: carbon element out of range");
+  for (int sp : {sd->precursor, sd->growth}) {
+    if (sp < 0 || sp >= N) return fail(PSR_EINVAL, "soot: species index out of range");
+    for (int e = 0; e < E; e++)
+      if ((e == sd->carbon) != (d->species_elems[sp * E + e] > 0))
+        return fail(PSR_EINVAL, "soot: precursor and growth species must be pure carbon");
+  }
+  if (sd->precursor == sd->growth) return fail(PSR_EINVAL, "soot: precursor and growth species coincide");
+  const double v[] = {sd->A_nuc, sd->beta_nuc, sd->E_nuc, sd->A_grow, sd->beta_grow, sd->E_grow,
+                      sd->site_density, sd->soot_density, sd->coag_scale};
+  for (double a : v)
+    if (!std::isfinite(a)) return fail(PSR_EINVAL, "soot: non-finite constant");
+  if (sd->A_nuc < 0 || sd->A_grow < 0 || sd->site_density < 0 || !(sd->soot_density > 0) ||
+      sd->coag_scale < 0)
+    return fail(PSR_EINVAL, "soot: negative rate constant or non-positive density");
+  frac.assign(6 * kSootOrders + 4, 0.0);
+  for (int q = 0; q < kSootOrders; q++) {
+    double p;
+    if (q < 24) p = (q / 3) + (q % 3 == 0 ? 1.0 / 6.0 : (q % 3 == 1 ? -1.0 / 6.0 : -0.5));
+    else p = (q - 24) + 2.0 / 3.0;
+    const int nodes = p >= 0.0 ? 6 : 3;
+    double *c = frac.data() + 6 * q;
+    for (int l = 1; l < nodes; l++) {
+      const double L = lagrange(p, l, nodes);
+      c[l] += L;
+      c[0] -= L;
+    }
+  }
+  for (int l = 0; l < 4; l++) frac[6 * kSootOrders + l] = lagrange(0.5, l, 4);
+  return PSR_OK;
 }
 
 extern "C" psr_status psr_create_mechanism(const psr_mech_desc *d, psr_mech_t *out) {
@@ -560,8 +610,16 @@ extern "C" psr_status psr_create_mechanism(const psr_mech_desc *d, psr_mech_t *o
     for (auto &pr : bysp[i]) { rx.push_back(pr.first); nu.push_back(pr.second); }
   }
   const int nnz = ptr[N];
+  // soot closure: d ln mu_p / d ln M_j of the fractional orders, then the
+  // weights L_l(1/2) of the coagulation interpolation over l = 0..3
+  const psr_soot_desc *sd = d->soot;
+  std::vector<double> frac;
+  if (sd) {
+    psr_status sst = soot_tables(d, frac);
+    if (sst != PSR_OK) return sst;
+  }
   // one blob: doubles first, then ints
-  const size_t nd = (size_t)N + 7 * N + 3 * I;
+  const size_t nd = (size_t)N + 7 * N + 3 * I + frac.size();
   // packed slot words for the wavefront engine (needs N <= 254, nu <= 15)
   bool packable = N <= 254;
   std::vector<int> pk(3 * (size_t)I + nnz, 0);
@@ -588,10 +646,11 @@ extern "C" psr_status psr_create_mechanism(const psr_mech_desc *d, psr_mech_t *o
   double *hd = reinterpret_cast<double *>(host.data());
   int *hi = reinterpret_cast<int *>(host.data() + nd * 8);
   size_t od = 0, oi = 0;
-  auto putd = [&](const double *src, size_t cnt) { memcpy(hd + od, src, cnt * 8); od += cnt; return od - cnt; };
+  auto putd = [&](const double *src, size_t cnt) { if (cnt) memcpy(hd + od, src, cnt * 8); od += cnt; return od - cnt; };
   auto puti = [&](const int *src, size_t cnt) { if (cnt) memcpy(hi + oi, src, cnt * 4); oi += cnt; return oi - cnt; };
   const size_t oW = putd(W.data(), N), oNasa = putd(d->nasa7, 7 * (size_t)N);
   const size_t olnA = putd(lnA.data(), I), obeta = putd(beta.data(), I), oEoR = putd(EoR.data(), I);
+  const size_t ofrac = putd(frac.data(), frac.size());
   const size_t odnu = puti(dnu.data(), I), orI = puti(ridx.data(), 3 * I), orN = puti(rnu.data(), 3 * I);
   const size_t opI = puti(pidx.data(), 3 * I), opN = puti(pnu.data(), 3 * I);
   const size_t optr = puti(ptr.data(), N + 1), orx = puti(rx.data(), nnz), onu = puti(nu.data(), nnz);
@@ -615,6 +674,23 @@ extern "C" psr_status psr_create_mechanism(const psr_mech_desc *d, psr_mech_t *o
   m->dev.p_idx = bi + opI; m->dev.p_nu = bi + opN;
   m->dev.sp_ptr = bi + optr; m->dev.sp_rx = bi + orx; m->dev.sp_nu = bi + onu;
   m->dev.packed = packable ? bi + opk : nullptr;
+  m->dev.soot = 0;
+  if (sd) {  // the wavefront engine has no soot rows: soot mechanisms use the block engine
+    const double kNA = 6.02214076e23, kB = 1.380649e-16, pi = 3.14159265358979323846;
+    const double mC = d->elem_weight[sd->carbon] / kNA;  // g per carbon atom
+    m->dev.packed = nullptr;
+    m->dev.soot = 1;
+    m->dev.sP = sd->precursor;
+    m->dev.sG = sd->growth;
+    m->dev.Cmin = 2.0 * d->species_elems[sd->precursor * E + sd->carbon];
+    m->dev.D = d->species_elems[sd->growth * E + sd->carbon];
+    m->dev.An = sd->A_nuc; m->dev.bn = sd->beta_nuc; m->dev.EnR = sd->E_nuc / kR;
+    m->dev.As = sd->A_grow; m->dev.bs = sd->beta_grow; m->dev.EsR = sd->E_grow / kR;
+    m->dev.KW = sd->site_density * pi * pow(6.0 * mC / (pi * sd->soot_density), 2.0 / 3.0);
+    m->dev.KF0 = sd->coag_scale * 2.2 * pow(3.0 * mC / (4.0 * pi * sd->soot_density), 1.0 / 6.0) *
+                 sqrt(6.0 * kB / sd->soot_density);
+    m->dev.frac = bd + ofrac;
+  }
   *out = m;
   return PSR_OK;
 }
@@ -628,7 +704,7 @@ extern "C" psr_status psr_destroy_mechanism(psr_mech_t m) {
 }
 
 extern "C" int32_t psr_num_unknowns(psr_mech_t m, int32_t energy) {
-  return m ? m->N + (energy ? 1 : 0) : -1;
+  return m ? n_unknowns(m->dev, energy) : -1;
 }
 
 // ------------------------------------------------------------ host: kernels
@@ -638,12 +714,13 @@ static psr_status check_cond(psr_mech_t m, const psr_conditions *c) {
   if (c->n_reactors <= 0) return fail(PSR_EINVAL, "n_reactors must be positive");
   if (c->n_reactors > 0x7fffffffLL) return fail(PSR_EUNSUPPORTED, "n_reactors above 2^31-1");
   if (!c->P || !c->tau || !c->T_in || !c->Y_in) return fail(PSR_EINVAL, "null condition pointer");
+  if (m->dev.soot && !c->energy) return fail(PSR_EINVAL, "a soot mechanism needs energy reactors");
   return PSR_OK;
 }
 
 static size_t layout_bytes(psr_mech_t m, int energy, bool mixed, bool split = false) {
   Layout L;
-  L.make(m->N, m->I, m->N + (energy ? 1 : 0), mixed, kBS, split);
+  L.make(m->N, m->I, n_unknowns(m->dev, energy), mixed, kBS, split);
   return (size_t)L.total * 8;
 }
 
@@ -651,9 +728,9 @@ static size_t layout_bytes(psr_mech_t m, int energy, bool mixed, bool split = fa
 // matrices in HBM (split).  Returns false if even the split layout exceeds
 // the LDS of one workgroup.
 static bool block_layout(psr_mech_t m, int energy, bool mixed, Layout &L) {
-  L.make(m->N, m->I, m->N + (energy ? 1 : 0), mixed, kBS, false);
+  L.make(m->N, m->I, n_unknowns(m->dev, energy), mixed, kBS, false);
   if ((size_t)L.total * 8 <= (size_t)lds_limit_bytes()) return true;
-  L.make(m->N, m->I, m->N + (energy ? 1 : 0), mixed, kBS, true);
+  L.make(m->N, m->I, n_unknowns(m->dev, energy), mixed, kBS, true);
   return (size_t)L.total * 8 <= (size_t)lds_limit_bytes();
 }
 
@@ -681,7 +758,7 @@ extern "C" psr_status psr_residual(psr_mech_t m, const psr_conditions *c, const 
   psr_status st = check_cond(m, c);
   if (st != PSR_OK) return st;
   if (!x || !F) return fail(PSR_EINVAL, "null x or F");
-  const int n = m->N + (c->energy ? 1 : 0);
+  const int n = n_unknowns(m->dev, c->energy);
   if (m->dev.packed && n <= 64) {
     const size_t lds = wk::align16(psr::wave::tables_bytes(m->N, m->I, m->nnz)) +
                        (size_t)wk::kWR * psr::wave::WArea<64>::species_doubles() * 8;
@@ -797,6 +874,7 @@ static Opts to_dev_opts(const psr_solve_opts *o) {
   d.nw_h_ratio = o->nw_h_ratio; d.nw_max_it = o->nw_max_it; d.nw_every = o->nw_every;
   d.max_lin = o->max_lin; d.max_refine = o->max_refine;
   d.refine_tol = o->refine_tol;
+  d.atol_lnM = o->atol_lnM; d.ts_atol_lnM = o->ts_atol_lnM;
   return d;
 }
 
@@ -813,7 +891,7 @@ struct WavePlan {
 
 static WavePlan wave_plan(psr_mech_t m, int energy, bool mixed, int engine) {
   WavePlan w;
-  const int n = m->N + (energy ? 1 : 0);
+  const int n = n_unknowns(m->dev, energy);
   if (engine == 1 || !m->dev.packed) return w;
   const int NP = wave_np(n);
   if (!NP) return w;
@@ -996,7 +1074,8 @@ static psr_status check_opts(const psr_solve_opts *o) {
       !(o->lambda_min > 0 && o->lambda_min <= 1) || !(o->T_min < o->T_max) || !(o->ts_rtol > 0) ||
       !(o->h0 > 0) || !(o->h_min > 0) || !(o->h_max > 0) || o->nw_max_it < 1 || o->nw_every < 1 ||
       o->max_lin < 1 || o->max_refine < 0 || o->engine < 0 || o->engine > 2 || o->use_graph < 0 ||
-      o->use_graph > 1 || !(o->refine_tol > 0 && o->refine_tol < 1))
+      o->use_graph > 1 || !(o->refine_tol > 0 && o->refine_tol < 1) || !(o->atol_lnM >= 0) ||
+      !(o->ts_atol_lnM >= 0))
     return fail(PSR_EINVAL, "option out of range");
   return PSR_OK;
 }

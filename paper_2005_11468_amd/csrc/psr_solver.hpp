@@ -32,7 +32,7 @@ __device__ inline double newton_norm(const Ctx &c, const Opts &o, const double *
                                      double *red) {
   double r = 0.0;
   for (int k = threadIdx.x; k < c.n; k += BS) {
-    const double w = (k < c.N ? o.atol_Y : o.atol_T) + o.rtol * fabs(x[k]);
+    const double w = (k < c.N ? o.atol_Y : (k == c.N ? o.atol_T : o.atol_lnM)) + o.rtol * fabs(x[k]);
     double t = fabs(v[k]) / w;
     if (t != t) t = __builtin_inf();
     r = fmax(r, t);
@@ -40,14 +40,15 @@ __device__ inline double newton_norm(const Ctx &c, const Opts &o, const double *
   return block_max<BS>(r, red);
 }
 
-// out = x + lam d, Y projected onto Y >= 0, T onto [T_min, T_max].
+// out = x + lam d, Y projected onto Y >= 0, T onto [T_min, T_max]; soot
+// ln M unbounded.
 template <int BS>
 __device__ inline void step_clamped(const Ctx &c, const Opts &o, const double *x, double lam,
                                     const double *d, double *out) {
   for (int i = threadIdx.x; i < c.n; i += BS) {
     double v = x[i] + lam * d[i];
     if (i < c.N) v = v > 0.0 ? v : 0.0;
-    else v = v < o.T_min ? o.T_min : (v > o.T_max ? o.T_max : v);
+    else if (i == c.N) v = v < o.T_min ? o.T_min : (v > o.T_max ? o.T_max : v);
     out[i] = v;
   }
   __syncthreads();
@@ -346,12 +347,12 @@ __device__ void round_step(Ctx &c, const Opts &o, RState &s) {
       for (int i = threadIdx.x; i < n; i += BS) {
         const double xn = x[i] + 1.5 * h * d[i] + 0.5 * h * t[i];
         const double ax = fmax(fabs(x[i]), fabs(xn));
-        const double w = (i < N ? o.ts_atol_Y : o.ts_atol_T) + o.ts_rtol * ax;
+        const double w = (i < N ? o.ts_atol_Y : (i == N ? o.ts_atol_T : o.ts_atol_lnM)) + o.ts_rtol * ax;
         const double e = 0.5 * h * (d[i] + t[i]) / w;
         e2 += e * e;
         bad |= !isfinite(xn);
         if (i < N) bad |= xn < -o.ts_neg_tol;
-        else bad |= (xn < o.T_min || xn > o.T_max);
+        else if (i == N) bad |= (xn < o.T_min || xn > o.T_max);
         xev[i] = xn;
       }
       const double err = sqrt(block_sum<BS>(e2, red) / n);

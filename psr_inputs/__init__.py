@@ -4,8 +4,10 @@ Holds no solver arithmetic: it draws mechanisms, reactor conditions and
 initial guesses, nothing else.
 """
 from .conditions import initial_guess, make_conditions
-from .configs import UNEVEN, WORKLOADS, mechanism, subset, uneven_workload, workload
+from .configs import (SOOT_CONSTANTS, UNEVEN, WORKLOADS, mechanism, soot_nucleus_size, subset,
+                      uneven_workload, workload)
 from .mechanism import make_mechanism, species_weights
 
 __all__ = ["make_mechanism", "species_weights", "make_conditions", "initial_guess",
-           "WORKLOADS", "UNEVEN", "mechanism", "workload", "uneven_workload", "subset"]
+           "WORKLOADS", "UNEVEN", "SOOT_CONSTANTS", "mechanism", "workload", "uneven_workload",
+           "subset", "soot_nucleus_size"]

@@ -21,6 +21,7 @@ import numpy as np
 from .mechanism import species_weights
 
 P_ATM = 101325.0
+M0_SOOT = 1e3  # initial soot number density, nuclei per cm^3
 
 
 def make_conditions(mech: dict, n_reactors: int, seed: int, *, recipe: str,
@@ -54,10 +55,16 @@ def make_conditions(mech: dict, n_reactors: int, seed: int, *, recipe: str,
     }
 
 
-def initial_guess(cond: dict, energy: bool, T0: float = 2000.0) -> np.ndarray:
-    """x0 = (Y_in[, T0]) in [n][B] layout; T0 = 2000 K aims at the ignited branch."""
+def initial_guess(cond: dict, energy: bool, T0: float = 2000.0, soot_nucleus=None) -> np.ndarray:
+    """x0 = (Y_in[, T0][, ln M_0..ln M_5]) in [n][B] layout; T0 = 2000 K aims
+    at the ignited branch.  With soot (nucleus of `soot_nucleus` carbon
+    atoms) the moments start as 1e3 nuclei per cm^3: ln M_r = ln 1e3 + r ln C."""
     Y = cond["Y_in"]
     if not energy:
         return Y.copy()
     B = Y.shape[1]
-    return np.concatenate([Y, np.full((1, B), float(T0))], axis=0)
+    rows = [Y, np.full((1, B), float(T0))]
+    if soot_nucleus is not None:
+        lnM = np.log(M0_SOOT) + np.arange(6) * np.log(float(soot_nucleus))
+        rows.append(np.repeat(lnM[:, None], B, axis=1))
+    return np.concatenate(rows, axis=0)

@@ -34,7 +34,17 @@ MECH_SPECS = {
     "uneven_a": (30, 200, 41, 0.6),
     "uneven_b": (100, 600, 49),
     "uneven_c": (200, 1200, 43),
+    "soot": (150, 900, 56),
 }
+
+# Soot model constants of the sooting workload (fixed, not drawn): nucleation
+# from two precursor molecules, surface growth by the C2 species, free-
+# molecular coagulation; carbon is element 0.  Rate constants in
+# cm^3/(mol s) with E in J/mol; site density in sites/cm^2; soot density
+# g/cm^3.
+SOOT_CONSTANTS = dict(carbon=0, A_nuc=1.0e9, beta_nuc=0.0, E_nuc=5.0e4,
+                      A_grow=1.0e9, beta_grow=0.0, E_grow=4.0e4,
+                      site_density=2.3e15, soot_density=1.8, coag_scale=1.0)
 
 # The uneven-batching workload: three mechanisms in one solve, 65536 reactors
 # split 50 / 35 / 15 %, tau log-uniform in [1e-6, 1] s, phi inlet; one
@@ -51,13 +61,21 @@ WORKLOADS = {
     # residual-kernel throughput batch (the paper's largest batch size, 1e6)
     "rate": dict(mech="mixed", B=1_000_000, seed=62, energy=True, recipe="phi",
                  tau_range=(1e-5, 1e-1)),
+    # sooting reactors: fuel-rich inlet (the paper's sooting case has
+    # equivalence ratio 2.5) and 6 soot moments per reactor
+    "soot": dict(mech="soot", B=8192, seed=52, energy=True, recipe="phi",
+                 tau_range=(1e-3, 1e-1), phi_range=(1.5, 3.0)),
 }
 
 
 @lru_cache(maxsize=None)
 def mechanism(name: str) -> dict:
     n_sp, n_rx, seed, *rest = MECH_SPECS[name]
-    return make_mechanism(n_sp, n_rx, seed, heat_scale=rest[0] if rest else 1.0)
+    soot = name == "soot"
+    mech = make_mechanism(n_sp, n_rx, seed, heat_scale=rest[0] if rest else 1.0, soot=soot)
+    if soot:
+        mech["soot"] = dict(precursor=mech["precursor"], growth=mech["growth"], **SOOT_CONSTANTS)
+    return mech
 
 
 def uneven_workload(fraction: float = 1.0):
@@ -85,10 +103,18 @@ def workload(name: str, n_reactors: int | None = None):
     B = spec["B"] if n_reactors is None else int(n_reactors)
     cond = make_conditions(mech, spec.get("B_draw", spec["B"]), spec["seed"],
                            recipe=spec["recipe"], tau_range=spec["tau_range"],
-                           T_in=spec.get("T_in"))
+                           T_in=spec.get("T_in"), phi_range=spec.get("phi_range", (0.5, 2.5)))
     cond = {k: np.ascontiguousarray(v[..., :B]) for k, v in cond.items()}
-    x0 = initial_guess(cond, spec["energy"])
+    x0 = initial_guess(cond, spec["energy"], soot_nucleus=soot_nucleus_size(mech))
     return mech, cond, x0, spec["energy"]
+
+
+def soot_nucleus_size(mech: dict):
+    """Carbon atoms per soot nucleus (two precursor molecules), or None."""
+    sd = mech.get("soot")
+    if sd is None:
+        return None
+    return 2 * int(mech["species_elems"][sd["precursor"], sd["carbon"]])
 
 
 def subset(cond: dict, x0: np.ndarray, idx) -> tuple[dict, np.ndarray]:

@@ -59,6 +59,10 @@ BOND_ENTHALPY = 1.0e5
 NOISE_ENTHALPY = 2.0e4
 FUEL_OX_OFFSET = 2.5e5
 PRODUCT_OFFSET = -2.5e5
+# Pure-carbon soot species (precursor, growth) are made more stable than the
+# bond rule alone gives, so that they are present at the fuel-rich steady
+# states where soot forms.
+SOOT_OFFSET = -1.0e5
 # Entropy recipe (dimensionless S/R near 1500 K): per-molecule + per-atom.
 S_PER_MOLECULE = 14.0
 S_PER_ATOM = 3.0
@@ -111,6 +115,8 @@ def _nasa7(rng, comps, roles, heat_scale=1.0):
         h[i] += heat_scale * FUEL_OX_OFFSET
     for i in roles.get("products", []):
         h[i] += heat_scale * PRODUCT_OFFSET
+    for i in roles.get("soot", []):
+        h[i] += SOOT_OFFSET
     a[:, 5] = h / R_GAS
     s_target = S_PER_MOLECULE + S_PER_ATOM * na + rng.uniform(-2.0, 2.0, n)
     a[:, 6] = s_target - a[:, 0] * LN_T_REF
@@ -156,6 +162,8 @@ def make_mechanism(n_species: int, n_reactions: int, seed: int, *, soot: bool = 
     oxid = 1
     products = [2, 3]
     roles = {"fuel_ox": [fuel, oxid], "products": products}
+    if soot:
+        roles["soot"] = [4, 5]
     nasa, h_offset = _nasa7(rng, comps, roles, heat_scale)
 
     tables = {s: _multiset_table(n_reactive, comps, s) for s in (1, 2, 3)}

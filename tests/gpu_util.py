@@ -15,12 +15,18 @@ def cond_dev(cond):
 
 
 def rel_err(a, b, n_species, floor=FLOOR_Y):
-    """max over components of |a - b| / max(|b|, floor) (floor on species only)."""
+    """max over components of |a - b| / max(|b|, floor) (floor on species
+    only); soot rows (ln M_r, after the temperature row) compare M_r = exp(ln M_r)
+    relatively: |exp(a - b) - 1|."""
     a = np.asarray(a, float)
     b = np.asarray(b, float)
-    den = np.abs(b).copy()
+    m = n_species + 1
+    den = np.abs(b[:m]).copy()
     den[:n_species] = np.maximum(den[:n_species], floor)
-    return np.max(np.abs(a - b) / den, axis=0)
+    e = np.abs(a[:m] - b[:m]) / den
+    if a.shape[0] > m:
+        e = np.concatenate([e, np.abs(np.expm1(a[m:] - b[m:]))], axis=0)
+    return np.max(e, axis=0)
 
 
 def solve_gpu(mech_obj, cond, x0, energy, **opts):
