@@ -158,6 +158,36 @@ def uneven(P, fraction=1.0 / 64):
             "lin_total": int(st.lin_total), "note": f"prefix fraction {fraction:g} of each group"}
 
 
+def soot(P, reactors=512):
+    """The sooting workload (150 species / 900 reactions + 6 soot moments,
+    n = 157, fuel-rich inlet) on a seeded prefix: mixed-precision persistent
+    solve against the plain FP64 solve of the same reactors."""
+    import torch
+    from psr_inputs import workload
+    from tests.gpu_util import cond_dev, dev
+    mech, cond, x0, _ = workload("soot", reactors)
+    B = x0.shape[1]
+    M = P.Mechanism(mech)
+    cd, x0d = cond_dev(cond), dev(x0)
+    out = {"reactors": B, "n": int(x0.shape[0])}
+    for name, o in (("mixed_persistent", P.default_opts(precision=P.PSR_MIXED, scheduler=P.PSR_PERSISTENT)),
+                    ("fp64_plain", P.default_opts(precision=P.PSR_FP64, scheduler=P.PSR_PLAIN))):
+        g = dict(mech=M, cond=cd, energy=True, x=x0d.clone(),
+                 status=torch.empty(B, dtype=torch.int32, device="cuda:0"),
+                 n_lin=torch.empty(B, dtype=torch.int32, device="cuda:0"))
+        st, ws = P.solve_batch([g], o, stats=True)  # warm-up (same inputs)
+        g["x"].copy_(x0d)
+        torch.cuda.synchronize()
+        st, _ = P.solve_batch([g], o, workspace=ws, stats=True)
+        torch.cuda.synchronize()
+        out[name] = {"converged": int(st.converged), "ms": st.kernel_ms,
+                     "converged_per_s": st.converged / (st.kernel_ms / 1e3), "lin_total": int(st.lin_total),
+                     "fp64_fallbacks": int(st.fp64_fallbacks)}
+        print(f"soot {name}: {st.converged}/{B} converged in {st.kernel_ms:.1f} ms", file=sys.stderr,
+              flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +200,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lu-large", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
+    ap.add_argument("--soot-reactors", type=int, default=512,
+                    help="prefix of the sooting workload to solve (0: skip)")
     ap.add_argument("--rate-reactors", type=int, default=1_000_000,
                     help="batch size of the residual-kernel measurement (0: skip)")
     args = ap.parse_args()
@@ -239,6 +271,7 @@ def main():
         rate = rate_kernel(P, args.rate_reactors)
     lu_big = lu_large(P) if not args.no_lu_large else None
     unev = uneven(P) if not args.no_uneven else None
+    soot_leg = soot(P, args.soot_reactors) if args.soot_reactors > 0 else None
 
     # oracle on a bounded sample: CPU baseline and parity reference
     cpu = None
@@ -302,6 +335,7 @@ def main():
         "rate_kernel": rate,
         "lu_large": lu_big,
         "uneven": unev,
+        "soot": soot_leg,
         "parity": parity,
         "cpu_baseline": cpu,
     }
