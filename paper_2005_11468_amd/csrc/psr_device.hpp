@@ -708,7 +708,9 @@ __device__ int lu_factor(T *A, int n, int lda, int *piv, double *red) {
 // to 256 rows (kept in HBM for the large mechanisms), panel width 16.
 //   panel:    the n - k0 by 16 panel is copied to LDS (pan, row stride 17);
 //             per column a block argmax (first maximum), a row interchange
-//             inside the panel and a rank-one update of the panel rows below;
+//             inside the panel and a rank-one update of the panel rows below
+//             (measured faster here, two workgroups per CU, than factoring
+//             the panel by one wavefront without block barriers);
 //   swaps:    the panel's row interchanges applied to the other columns
 //             (one column per thread);
 //   U12:      L11^-1 A12 by forward substitution, one column per thread, L11
