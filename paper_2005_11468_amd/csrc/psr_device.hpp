@@ -861,6 +861,122 @@ __device__ __forceinline__ int lu_factor_mfma32(float *A, int n, int lda, int *p
   return 0;
 }
 
+// Blocked right-looking FP64 LU with partial pivoting for matrices kept in
+// HBM (64 < n <= BS), panel width 16.  Same panel as lu_factor_mfma32 (copied
+// to LDS, block argmax with the first-maximum rule, row interchange and
+// rank-one update per column), then one column per thread: the panel's
+// interchanges, U12 = L11^-1 A12 by forward substitution (kept in
+// registers) and the trailing update A22 -= L21 U12 of that column, reading
+// L21 from the panel in LDS.  The trailing matrix is read and written once
+// per panel instead of once per column.  pan: LDS scratch of at least 17 n
+// doubles.  Returns 0 or k+1.
+template <int BS>
+__device__ __forceinline__ int lu_factor_blocked64(double *A, int n, int lda, int *piv, double *red, double *pan) {
+  static_assert(BS == 256, "one panel row and one column per thread");
+  constexpr int PS = 17;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double *wval = red + 16;
+  int *widx = reinterpret_cast<int *>(red + 20);
+  for (int k0 = 0; k0 < n; k0 += 16) {
+    const int kb = n - k0 < 16 ? n - k0 : 16;
+    const int rows = n - k0;
+    for (int e = tid; e < rows * 16; e += BS) {
+      const int t = e >> 4, j = e & 15;
+      pan[t * PS + j] = j < kb ? A[(int64_t)(k0 + t) * lda + k0 + j] : 0.0;
+    }
+    __syncthreads();
+    for (int jj = 0; jj < kb; jj++) {
+      const int k = k0 + jj;
+      double v = (tid < rows && tid >= jj) ? fabs(pan[tid * PS + jj]) : -1.0;
+      int vi = tid;
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(v, off);
+        const int oi = __shfl_xor(vi, off);
+        if (ov > v || (ov == v && oi < vi)) { v = ov; vi = oi; }
+      }
+      if (lane == 0) { wval[wv] = v; widx[wv] = vi; }
+      __syncthreads();
+      double best = wval[0];
+      int bi = widx[0];
+      for (int w = 1; w < BS / 64; w++)
+        if (wval[w] > best || (wval[w] == best && widx[w] < bi)) { best = wval[w]; bi = widx[w]; }
+      if (!(best > 0.0)) {
+        __syncthreads();
+        return k + 1;
+      }
+      if (tid == 0) piv[k] = k0 + bi;
+      if (bi != jj && tid < 16) {
+        const double t = pan[jj * PS + tid];
+        pan[jj * PS + tid] = pan[bi * PS + tid];
+        pan[bi * PS + tid] = t;
+      }
+      __syncthreads();
+      if (tid < rows && tid > jj) {
+        const double l = pan[tid * PS + jj] / pan[jj * PS + jj];
+        pan[tid * PS + jj] = l;
+        for (int j = jj + 1; j < kb; j++) pan[tid * PS + j] -= l * pan[jj * PS + j];
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < rows * 16; e += BS) {
+      const int t = e >> 4, j = e & 15;
+      if (j < kb) A[(int64_t)(k0 + t) * lda + k0 + j] = pan[t * PS + j];
+    }
+    const int R0 = k0 + kb;
+    const int c = tid;
+    if (c < n && (c < k0 || c >= R0)) {
+      int pr[16];
+#pragma unroll
+      for (int jj = 0; jj < 16; jj++) pr[jj] = jj < kb ? piv[k0 + jj] : k0 + jj;
+#pragma unroll
+      for (int jj = 0; jj < 16; jj++) {
+        if (jj < kb && pr[jj] != k0 + jj) {
+          double *x = A + (int64_t)(k0 + jj) * lda + c, *y = A + (int64_t)pr[jj] * lda + c;
+          const double t = *x;
+          *x = *y;
+          *y = t;
+        }
+      }
+      if (c >= R0) {
+        double u[16];
+#pragma unroll
+        for (int i = 0; i < 16; i++) u[i] = i < kb ? A[(int64_t)(k0 + i) * lda + c] : 0.0;
+#pragma unroll
+        for (int i = 1; i < 16; i++) {
+          double acc = u[i];
+#pragma unroll
+          for (int q = 0; q < 16; q++)
+            if (q < i) acc -= (i < kb ? pan[i * PS + q] : 0.0) * u[q];
+          u[i] = acc;
+        }
+#pragma unroll
+        for (int i = 0; i < 16; i++)
+          if (i < kb) A[(int64_t)(k0 + i) * lda + c] = u[i];
+        // trailing update of this column, four rows in flight
+        for (int i0 = R0; i0 < n; i0 += 4) {
+          double a[4];
+#pragma unroll
+          for (int r = 0; r < 4; r++) a[r] = i0 + r < n ? A[(int64_t)(i0 + r) * lda + c] : 0.0;
+#pragma unroll
+          for (int r = 0; r < 4; r++) {
+            const double *lrow = pan + ((i0 + r < n ? i0 + r : n - 1) - k0) * PS;
+            double acc = a[r];
+#pragma unroll
+            for (int q = 0; q < 16; q++)
+              if (q < kb) acc -= lrow[q] * u[q];
+            a[r] = acc;
+          }
+#pragma unroll
+          for (int r = 0; r < 4; r++)
+            if (i0 + r < n) A[(int64_t)(i0 + r) * lda + c] = a[r];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  return 0;
+}
+
 template <int BS, typename T>
 __device__ void lu_solve(const T *A, int n, int lda, const int *piv, double *b) {
   const int tid = threadIdx.x;

@@ -105,6 +105,17 @@ __device__ int factor_mixed(const Ctx &c, const double *A64, float *A32, int *pi
   return lu_factor<BS, float>(A32, n, lda, piv, red);
 }
 
+// FP64 factorisation of the round's matrix.  Large matrices (kept in HBM)
+// use the blocked LU, whose panel borrows the reaction scratch in LDS (not in
+// use between the Jacobian and the next residual).
+template <int BS, bool BIG>
+__device__ inline int factor64(const Ctx &c, double *A64, int *piv, double *red) {
+  const int n = c.n, lda = c.L.lda;
+  if (BIG && BS == 256 && n > 64 && n <= 256 && 12 * c.L.I >= 17 * n)
+    return lu_factor_blocked64<256>(A64, n, lda, piv, red, c.p(c.L.kf));
+  return lu_factor<BS, double>(A64, n, lda, piv, red);
+}
+
 // z = A^-1 b with the float factors of the equilibrated matrix.
 template <int BS>
 __device__ inline void solve_scaled32(const Ctx &c, const float *A32, const int *piv, const double *rs,
@@ -123,7 +134,7 @@ __device__ inline void solve_scaled32(const Ctx &c, const float *A32, const int 
 // is below tol of |z| in max norm; if the correction shrinks by less
 // than half, or max_refine sweeps do not reach that, the matrix is
 // refactored in FP64 for the rest of this linearisation.
-template <int BS, bool MIXED>
+template <int BS, bool MIXED, bool BIG>
 __device__ void solve_round(const Ctx &c, const Opts &o, RState &s, const double *b, double *z, double tol) {
   const int n = c.n, lda = c.L.lda;
   double *red = c.p(c.L.red);
@@ -166,7 +177,7 @@ __device__ void solve_round(const Ctx &c, const Opts &o, RState &s, const double
   // FP64 fallback for this matrix
   s.fb64 = 1;
   s.n_fb64++;
-  const int info = lu_factor<BS, double>(A64, n, lda, piv, red);
+  const int info = factor64<BS, BIG>(c, A64, piv, red);
   s.sing = info != 0;
   vcopy<BS>(z, bb, n);
   if (!s.sing) lu_solve<BS, double>(A64, n, lda, piv, z);
@@ -250,10 +261,10 @@ __device__ void round_step(Ctx &c, const Opts &o, RState &s) {
         if (info != 0) {
           s.fb64 = 1;
           s.n_fb64++;
-          s.sing = lu_factor<BS, double>(A64, n, lda, piv, red) != 0;
+          s.sing = factor64<BS, BIG>(c, A64, piv, red) != 0;
         }
       } else {
-        s.sing = lu_factor<BS, double>(A64, n, lda, piv, red) != 0;
+        s.sing = factor64<BS, BIG>(c, A64, piv, red) != 0;
       }
     }
   }
@@ -271,7 +282,7 @@ __device__ void round_step(Ctx &c, const Opts &o, RState &s) {
     double *out = (ph == PH_NW_BASE || ph == PH_TS1) ? d : t;
     double tol = o.refine_tol;
     for (;;) {
-      solve_round<BS, MIXED>(c, o, s, G, out, tol);
+      solve_round<BS, MIXED, BIG>(c, o, s, G, out, tol);
       // a Newton step that would end the solve must rest on a tightly refined solve
       if (MIXED && ph == PH_NW_BASE && !s.sing && !s.fb64 && tol > kFinalRefine && sres <= o.ftol &&
           all_finite<BS>(out, n, red) && newton_norm<BS>(c, o, xnw, out, red) <= 1.0) {
