@@ -177,6 +177,7 @@ __device__ void solve_round(const Ctx &c, const Opts &o, RState &s, const double
   // FP64 fallback for this matrix
   s.fb64 = 1;
   s.n_fb64++;
+  s.stick = kStickFP64;
   const int info = factor64<BS, BIG>(c, A64, piv, red);
   s.sing = info != 0;
   vcopy<BS>(z, bb, n);
@@ -255,12 +256,18 @@ __device__ void round_step(Ctx &c, const Opts &o, RState &s) {
     s.fin = all_finite<BS>(G, n, red) && matrix_finite<BS>(A64, n, lda, red);
     s.sing = 0;
     if (s.fin) {
-      if (MIXED) {
+      if (MIXED && s.stick > 0) {  // recent fallback: FP64 directly
+        s.stick--;
+        s.fb64 = 1;
+        s.n_fb64++;
+        s.sing = factor64<BS, BIG>(c, A64, piv, red) != 0;
+      } else if (MIXED) {
         const int info = factor_mixed<BS, BIG>(c, A64, c.A32(), piv,
                                           c.p(L.rs), c.p(L.cs), red);
         if (info != 0) {
           s.fb64 = 1;
           s.n_fb64++;
+          s.stick = kStickFP64;
           s.sing = factor64<BS, BIG>(c, A64, piv, red) != 0;
         }
       } else {
@@ -397,7 +404,7 @@ __device__ inline void init_state(const Ctx &c, const Opts &o, RState &s) {
   s.phase = PH_NW_BASE;
   s.status = RS_RUNNING;
   s.n_lin = s.n_jac = s.n_ts = s.n_att = s.nw_it = s.accepted = 0;
-  s.fb64 = s.n_fb64 = s.sing = 0;
+  s.fb64 = s.n_fb64 = s.sing = s.stick = 0;
   s.fin = 1;
   s.nd = s.lam = s.sres = 0.0;
   s.h = o.h0 * c.tau;

@@ -371,7 +371,7 @@ __device__ __forceinline__ void init_w(const WCtx &c, const Opts &o, WState<NP, 
   s.phase = PH_NW_BASE;
   s.status = RS_RUNNING;
   s.n_lin = s.n_jac = s.n_ts = s.n_att = s.nw_it = s.accepted = 0;
-  s.fb64 = s.n_fb64 = s.sing = 0;
+  s.fb64 = s.n_fb64 = s.sing = s.stick = 0;
   s.fin = 1;
   s.nd = s.lam = s.sres = 0.0;
   s.h = o.h0 * c.tau;

@@ -122,3 +122,29 @@ def test_rejects_null_and_empty(lib):
     assert lib.psr_solve_batch(None, 0, C.byref(o), None, 0, None, None) == 1
     o.precision = 7
     assert lib.psr_solve_batch(None, 0, C.byref(o), None, 0, None, None) == 1
+
+
+def test_rejects_bad_soot_description(lib):
+    """Soot descriptions are validated before anything touches the device:
+    the precursor and growth species must be pure carbon and distinct, the
+    indices in range, the densities positive."""
+    from paper_2005_11468_amd import _lib
+    from psr_inputs import SOOT_CONSTANTS, mechanism
+    mech = mechanism("soot")
+    good = dict(mech["soot"])
+    not_carbon = int(np.flatnonzero(mech["species_elems"][:, 1] > 0)[0])  # a species with hydrogen
+    cases = [(dict(good, precursor=not_carbon), "pure carbon"),
+             (dict(good, growth=good["precursor"]), "coincide"),
+             (dict(good, growth=10 ** 6), "out of range"),
+             (dict(good, carbon=5), "out of range"),
+             (dict(good, soot_density=0.0), "density"),
+             (dict(good, A_nuc=float("nan")), "non-finite")]
+    for sd, words in cases:
+        d, keep = _desc(mech)
+        s = _lib.SootDesc(*(sd[k] for k, _ in _lib.SootDesc._fields_))
+        d.soot = C.pointer(s)
+        h = C.c_void_p()
+        st = lib.psr_create_mechanism(C.byref(d), C.byref(h))
+        msg = lib.psr_last_error().decode()
+        assert st == 1 and words in msg, (sd, msg)
+    assert set(SOOT_CONSTANTS) <= set(good)
