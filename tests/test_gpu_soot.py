@@ -134,9 +134,13 @@ def test_soot_solve_matches_oracle(P, oracle_mod, sample, precision):
         assert r <= 1e-9, (int(b), r)
 
 
-def test_soot_schedulers_agree_bitwise(P, sample):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_soot_schedulers_agree_bitwise(P, sample, precision):
+    """Plain and persistent scheduling give identical results, also in mixed
+    precision, where the controller state carried between rounds includes
+    the FP64-fallback bookkeeping."""
     mech, cond, x0, _, _ = sample
-    a = _solve(P, mech, cond, x0, precision=0, scheduler=P.PSR_PERSISTENT)
-    b = _solve(P, mech, cond, x0, precision=0, scheduler=P.PSR_PLAIN)
+    a = _solve(P, mech, cond, x0, precision=precision, scheduler=P.PSR_PERSISTENT)
+    b = _solve(P, mech, cond, x0, precision=precision, scheduler=P.PSR_PLAIN)
     assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
     assert np.array_equal(a[0], b[0])
