@@ -38,7 +38,7 @@ typedef enum {
   PSR_EINVAL = 1,       /* invalid argument or mechanism                    */
   PSR_ENOMEM = 2,       /* device allocation failed / workspace too small    */
   PSR_EDEVICE = 3,      /* a HIP call failed                                 */
-  PSR_EUNSUPPORTED = 4  /* valid request outside what this build supports    */
+  PSR_EUNSUPPORTED = 4  /* valid request outside what this library supports  */
 } psr_status;
 
 /* Per-reactor outcome written to psr_group.status. */
