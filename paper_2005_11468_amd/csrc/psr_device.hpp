@@ -62,10 +62,9 @@ struct Opts {
 // Mixed precision: refinement target of the solve whose Newton step ends a
 // reactor's solve (the loose opts.refine_tol only steers the iteration).
 constexpr double kFinalRefine = 1e-10;
-// Mixed precision, workgroup engine: after a matrix needed the FP64
-// fallback, this many following linearisations of the reactor are factored
-// in FP64 directly (the float attempt on a matrix that ill-conditioned would
-// be wasted).
+// Mixed precision: after a matrix needed the FP64 fallback, this many
+// following linearisations of the reactor are factored in FP64 directly (the
+// float attempt on a matrix that ill-conditioned would be wasted).
 constexpr int kStickFP64 = 4;
 
 enum Phase : int { PH_NW_BASE = 0, PH_NW_TRIAL = 1, PH_TS1 = 2, PH_TS2 = 3, PH_DONE = 4 };
@@ -76,7 +75,7 @@ struct RState {
   int phase, status, n_lin, n_jac, n_ts, n_att, nw_it, accepted;
   int fb64;      // mixed mode: current matrix refactored in FP64
   int n_fb64;    // mixed mode: FP64 fallbacks so far
-  int stick;     // mixed mode, workgroup engine: linearisations still to factor in FP64 directly
+  int stick;     // mixed mode: linearisations still to factor in FP64 directly
   int sing, fin; // matrix flags of this round
   double nd, lam, h, sres;
 };

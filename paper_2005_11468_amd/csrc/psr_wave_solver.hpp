@@ -183,6 +183,7 @@ __device__ __forceinline__ double solve_w(const WCtx &c, const WArea<NP> &A, con
     if (fallback) {
       r.s.fb64 = 1;
       r.s.n_fb64++;
+      r.s.stick = kStickFP64;
       r.s.sing = factor64<NP, MIXED>(c, A, r) != 0;
       if (r.s.sing) return __builtin_nan("");
       fp64 = true;
@@ -236,9 +237,14 @@ __device__ __forceinline__ void w_round(const WCtx &c, const WArea<NP> &A, const
     s.sing = 0;
     if (s.fin) {
       if (MIXED) {
-        if (factor32<NP, MIXED>(c, A, r) != 0) {
+        // after a recent fallback the float attempt is skipped (one call
+        // site of each factorisation either way)
+        const bool direct = s.stick > 0;
+        if (direct) s.stick--;
+        if (direct || factor32<NP, MIXED>(c, A, r) != 0) {
           s.fb64 = 1;
           s.n_fb64++;
+          if (!direct) s.stick = kStickFP64;
           s.sing = factor64<NP, MIXED>(c, A, r) != 0;
         }
       } else {
