@@ -202,6 +202,8 @@ def main():
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--soot-reactors", type=int, default=512,
                     help="prefix of the sooting workload to solve (0: skip)")
+    ap.add_argument("--tune-sample", type=int, default=4096,
+                    help="reactors the autotuner times each launch shape on (0: automatic shape)")
     ap.add_argument("--rate-reactors", type=int, default=1_000_000,
                     help="batch size of the residual-kernel measurement (0: skip)")
     args = ap.parse_args()
@@ -252,6 +254,16 @@ def main():
         return ms, wall / steps, st, ws
 
     mixed = P.default_opts(precision=P.PSR_MIXED, scheduler=P.PSR_PERSISTENT)
+    tune = None
+    if args.tune_sample > 0:
+        # launch shape picked by the autotuner on a prefix of the batch (setup,
+        # outside the timed region)
+        t0 = time.perf_counter()
+        r = P.autotune(group, mixed, sample=args.tune_sample)
+        tune = {"engine": r.engine, "rpw": r.rpw, "grid_per_cu": r.grid_per_cu,
+                "candidates": r.candidates, "sample": min(args.tune_sample, B),
+                "sample_ms": r.ms, "default_shape_sample_ms": r.default_ms,
+                "tuning_s": time.perf_counter() - t0}
     ms_mixed, wall_mixed, st_mixed, ws = run(mixed, args.steps, args.warmup)
     x_mixed = x.cpu().numpy()
     s_mixed = status.cpu().numpy()
@@ -309,6 +321,10 @@ def main():
     lin_f, rnd_f = alg_flops(n, N, I)
     flops = st_mixed.jac_total * lin_f + st_mixed.lin_total * rnd_f
     achieved = flops / (st_mixed.kernel_ms / 1e3) / 1e12
+    # the counters were taken with the automatic launch shape of the wavefront
+    # engine; another shape moves other bytes
+    auto_shape = mixed.engine == 0 and mixed.rpw == 0 and mixed.grid_per_cu == 0
+    kname = "k_wpersist<64,mixed>" if mixed.engine != 1 else "k_persistent<mixed,n<=64>"
     out = {
         "metric": "converged PSR solves/sec (1 GPU), mixed-prec batched vs plain FP64, rel err<=1e-7",
         "value": value, "unit": "reactor-solves/s", "n_gpus": 1, "steps": args.steps,
@@ -318,7 +334,7 @@ def main():
         "config": {"workload": "mixed: 53 species / 325 reactions + energy, 16384 reactors",
                    "reactors": B, "species": N, "reactions": I, "unknowns": n,
                    "precision": "mixed (FP32 LU + FP64 refinement, FP64 residual)",
-                   "scheduler": "persistent work queue"},
+                   "scheduler": "persistent work queue", "launch_shape": tune},
         "fp64_plain": {"value": value_plain, "ms_per_step": ms_plain,
                        "converged": conv_plain, "rounds": st_plain.rounds,
                        "speedup_mixed_over_plain": value / value_plain if value_plain else None},
@@ -328,9 +344,10 @@ def main():
         "solver": {"converged": conv_mixed, "reactors": B, "lin_total": st_mixed.lin_total,
                    "lin_max": st_mixed.lin_max, "jac_total": st_mixed.jac_total,
                    "fp64_fallbacks": st_mixed.fp64_fallbacks, "wall_ms_per_step": wall_mixed * 1e3},
-        "roofline": {"kernel": "k_wpersist<64,mixed>", "bound": "alu", "achieved": achieved,
+        "roofline": {"kernel": kname, "bound": "alu", "achieved": achieved,
                      "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
-                     "traffic": SOLVE_TRAFFIC_BYTES, "kernel_ms": st_mixed.kernel_ms,
+                     "traffic": SOLVE_TRAFFIC_BYTES if auto_shape else None,
+                     "kernel_ms": st_mixed.kernel_ms,
                      "alg_flops": flops},
         "rate_kernel": rate,
         "lu_large": lu_big,

@@ -195,6 +195,15 @@ typedef struct {
   double refine_tol;
   /* soot: step-norm and local-error weight offsets of the ln M_r unknowns */
   double atol_lnM, ts_atol_lnM;
+  /* launch shape, 0 = automatic (psr_autotune measures and picks these):
+   * rpw: wavefront engine, reactors (one wavefront each) per workgroup that
+   * share one LDS copy of the mechanism tables, 1, 2 or 4; when the asked
+   * number does not fit the LDS the largest smaller one that fits is used.
+   * grid_per_cu: persistent scheduler, resident workgroups per compute unit
+   * (1..32), capped by what fits.  Results are bitwise independent of both;
+   * they change only speed. */
+  int32_t rpw;
+  int32_t grid_per_cu;
 } psr_solve_opts;
 
 /* Fill opts with the defaults (FP64, plain scheduler, graph replay on,
@@ -233,6 +242,38 @@ size_t psr_workspace_bytes(const psr_group *groups, int32_t n_groups, const psr_
 psr_status psr_solve_batch(const psr_group *groups, int32_t n_groups, const psr_solve_opts *opts,
                            void *workspace, size_t workspace_bytes, psr_solve_stats *stats,
                            void *stream);
+
+/* Outcome of psr_autotune. */
+typedef struct {
+  int32_t engine, rpw, grid_per_cu; /* the chosen launch shape (as in opts)       */
+  int32_t candidates;               /* shapes timed; 0 = taken from the cache     */
+  double ms;                        /* sample solve time of the chosen shape      */
+  double solves_per_s;              /* converged sample reactors per second       */
+  double default_ms;                /* sample solve time of the automatic shape
+                                       (0 when taken from the cache)              */
+} psr_tune_result;
+
+/* Launch-shape autotuner for the batch scheduling of the solve (the reactors
+ * are independent, paper §1 and §4, so only speed depends on how they are
+ * packed onto the GPU).  Solves the first `sample` reactors of every group
+ * (1 <= sample; larger than a group's size means the whole group) under each
+ * candidate shape -- engine (wavefront engine where it fits, or one
+ * workgroup per reactor), rpw, and for the persistent scheduler grid_per_cu
+ * -- one untimed run then the best of two timed ones, and writes the shape
+ * with the most converged reactor-solves per second into opts->engine,
+ * opts->rpw and opts->grid_per_cu (the other fields of opts are used as
+ * given).  The caller's x_inout, status and n_lin are not touched: the
+ * sample runs on copies.  cache_path (may be NULL): a text file of earlier
+ * results, one line per key (device, compute units, each group's mechanism
+ * sizes, energy flag and sample size, precision, scheduler); a hit is used
+ * without timing, a miss is appended.  Allocates and frees its own device
+ * buffers (not for use under stream capture); synchronises `stream`.
+ * result (host, optional) receives the choice.  Errors: PSR_EINVAL for bad
+ * arguments or an unreadable/unwritable cache file, PSR_EDEVICE for HIP
+ * failures, any error of psr_solve_batch for a candidate that every shape
+ * rejects. */
+psr_status psr_autotune(const psr_group *groups, int32_t n_groups, psr_solve_opts *opts, int64_t sample,
+                        const char *cache_path, psr_tune_result *result, void *stream);
 
 /* Message for the last non-OK status on this thread ("" if none). */
 const char *psr_last_error(void);

@@ -15,7 +15,7 @@ from ._lib import (PSR_FP64, PSR_MIXED, PSR_PERSISTENT, PSR_PLAIN, STATUS_NAMES,
                    SolveOpts, SolveStats)
 
 __all__ = ["Mechanism", "residual", "jacobian", "lu_factor_batch", "lu_solve_batch",
-           "solve_batch", "default_opts", "workspace_bytes", "PSR_FP64", "PSR_MIXED",
+           "solve_batch", "default_opts", "workspace_bytes", "autotune", "PSR_FP64", "PSR_MIXED",
            "PSR_PLAIN", "PSR_PERSISTENT", "STATUS_NAMES", "PSRError"]
 
 
@@ -200,3 +200,16 @@ def solve_batch(groups, opts: SolveOpts | None = None, workspace=None, stats: bo
                           C.byref(st) if st is not None else None, _stream(stream))
     _lib.check(r, "psr_solve_batch")
     return st, workspace
+
+
+def autotune(groups, opts: SolveOpts, sample: int = 4096, cache_path: str | None = None, stream=None):
+    """psr_autotune: times candidate launch shapes on the first `sample`
+    reactors of each group (on copies) and writes the fastest into opts
+    (engine, rpw, grid_per_cu).  Returns the TuneResult."""
+    G = _Groups(groups)
+    res = _lib.TuneResult()
+    r = _lib.load().psr_autotune(G.arr, G.n, C.byref(opts), int(sample),
+                                 cache_path.encode() if cache_path else None, C.byref(res),
+                                 _stream(stream))
+    _lib.check(r, "psr_autotune")
+    return res

@@ -47,7 +47,8 @@ class SolveOpts(C.Structure):
                 ("nw_max_it", C.c_int32), ("nw_every", C.c_int32), ("max_lin", C.c_int32),
                 ("max_refine", C.c_int32), ("engine", C.c_int32),
                 ("use_graph", C.c_int32), ("refine_tol", C.c_double),
-                ("atol_lnM", C.c_double), ("ts_atol_lnM", C.c_double)]
+                ("atol_lnM", C.c_double), ("ts_atol_lnM", C.c_double),
+                ("rpw", C.c_int32), ("grid_per_cu", C.c_int32)]
 
 
 class Group(C.Structure):
@@ -58,6 +59,12 @@ class SolveStats(C.Structure):
     _fields_ = [("reactors", C.c_int64), ("converged", C.c_int64), ("lin_total", C.c_int64),
                 ("lin_max", C.c_int64), ("jac_total", C.c_int64), ("fp64_fallbacks", C.c_int64),
                 ("rounds", C.c_int32), ("kernel_ms", C.c_double)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("engine", C.c_int32), ("rpw", C.c_int32), ("grid_per_cu", C.c_int32),
+                ("candidates", C.c_int32), ("ms", C.c_double), ("solves_per_s", C.c_double),
+                ("default_ms", C.c_double)]
 
 
 SYMBOLS = {
@@ -72,6 +79,8 @@ SYMBOLS = {
     "psr_workspace_bytes": ([C.POINTER(Group), C.c_int32, C.POINTER(SolveOpts)], C.c_size_t),
     "psr_solve_batch": ([C.POINTER(Group), C.c_int32, C.POINTER(SolveOpts), vp, C.c_size_t,
                          C.POINTER(SolveStats), vp], C.c_int),
+    "psr_autotune": ([C.POINTER(Group), C.c_int32, C.POINTER(SolveOpts), C.c_int64, C.c_char_p,
+                      C.POINTER(TuneResult), vp], C.c_int),
     "psr_last_error": ([], C.c_char_p),
 }
 

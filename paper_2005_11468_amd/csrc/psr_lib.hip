@@ -758,8 +758,9 @@ static bool block_layout(psr_mech_t m, int energy, bool mixed, Layout &L) {
   return (size_t)L.total * 8 <= (size_t)lds_limit_bytes();
 }
 
-// Resident workgroups of the block engine's persistent kernel.
-static int64_t block_grid(const Layout &L, bool mixed, int64_t B) {
+// Resident workgroups of the block engine's persistent kernel (at most
+// per_cu_cap per compute unit when it is positive).
+static int64_t block_grid(const Layout &L, bool mixed, int64_t B, int per_cu_cap) {
   const bool big = L.n > 64;
   int dev = 0, ncu = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -773,6 +774,7 @@ static int64_t block_grid(const Layout &L, bool mixed, int64_t B) {
     e = big ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<false, true>, kBS, lds)
             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<false, false>, kBS, lds);
   if (e != hipSuccess) return 0;
+  if (per_cu_cap > 0) per_cu = std::min(per_cu, per_cu_cap);
   if (per_cu < 1) per_cu = 1;
   return std::min<int64_t>(B, (int64_t)ncu * per_cu);
 }
@@ -926,11 +928,14 @@ static int wave_np(int n) { return n <= 16 ? 16 : (n <= 32 ? 32 : (n <= 64 ? 64 
 
 struct WavePlan {
   int NP = 0, rpw = 0;
+  int per_cu_cap = 0;  // persistent grid: workgroups per compute unit (0 = all that fit)
   size_t lds = 0;
   int stride = 0;  // plain scheduler area, doubles per reactor
 };
 
-static WavePlan wave_plan(psr_mech_t m, int energy, bool mixed, int engine) {
+// rpw_req: wavefronts per workgroup asked for (0 = the most that fit); the
+// largest of 4, 2, 1 not above it that fits the LDS is taken.
+static WavePlan wave_plan(psr_mech_t m, int energy, bool mixed, int engine, int rpw_req = 0) {
   WavePlan w;
   const int n = n_unknowns(m->dev, energy);
   if (engine == 1 || !m->dev.packed) return w;
@@ -945,6 +950,7 @@ static WavePlan wave_plan(psr_mech_t m, int energy, bool mixed, int engine) {
   }
   const size_t lim = (size_t)lds_limit_bytes();
   for (int rpw = 4; rpw >= 1; rpw /= 2) {
+    if (rpw_req > 0 && rpw > rpw_req) continue;
     if (tb + rpw * per <= lim) {
       w.NP = NP;
       w.rpw = rpw;
@@ -1033,6 +1039,7 @@ static psr_status launch_wave(const GroupDev &gd, const Opts &od, const WavePlan
     HIP_OK(hipGetDevice(&dev));
     HIP_OK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wk::k_wpersist<NP, MIXED>, threads, w.lds));
+    if (w.per_cu_cap > 0) per_cu = std::min(per_cu, w.per_cu_cap);
     if (per_cu < 1) per_cu = 1;
     const int64_t need = (B + w.rpw - 1) / w.rpw;
     const int64_t grid = std::min<int64_t>(need, (int64_t)ncu * per_cu);
@@ -1086,11 +1093,11 @@ static size_t group_ws(const psr_group &g, const psr_solve_opts *o) {
   const bool mixed = o->precision == PSR_MIXED;
   block_layout(g.mech, g.cond.energy, mixed, L);
   size_t bytes = align256(sizeof(RState) * (size_t)g.cond.n_reactors) + 256;
-  const WavePlan w = wave_plan(g.mech, g.cond.energy, mixed, o->engine);
+  const WavePlan w = wave_plan(g.mech, g.cond.energy, mixed, o->engine, o->rpw);
   if (o->scheduler == PSR_PLAIN)
     bytes += align256((size_t)(w.NP ? w.stride : L.persist + L.mat_total) * 8 * g.cond.n_reactors);
   else if (!w.NP && L.split)
-    bytes += align256((size_t)L.mat_total * 8 * block_grid(L, mixed, g.cond.n_reactors));
+    bytes += align256((size_t)L.mat_total * 8 * block_grid(L, mixed, g.cond.n_reactors, o->grid_per_cu));
   return bytes;
 }
 
@@ -1116,7 +1123,8 @@ static psr_status check_opts(const psr_solve_opts *o) {
       !(o->h0 > 0) || !(o->h_min > 0) || !(o->h_max > 0) || o->nw_max_it < 1 || o->nw_every < 1 ||
       o->max_lin < 1 || o->max_refine < 0 || o->engine < 0 || o->engine > 2 || o->use_graph < 0 ||
       o->use_graph > 1 || !(o->refine_tol > 0 && o->refine_tol < 1) || !(o->atol_lnM >= 0) ||
-      !(o->ts_atol_lnM >= 0))
+      !(o->ts_atol_lnM >= 0) || !(o->rpw == 0 || o->rpw == 1 || o->rpw == 2 || o->rpw == 4) ||
+      o->grid_per_cu < 0 || o->grid_per_cu > 32)
     return fail(PSR_EINVAL, "option out of range");
   return PSR_OK;
 }
@@ -1139,7 +1147,8 @@ static psr_status prepare_group(const psr_group &g, const psr_solve_opts *o, voi
   r.mixed = o->precision == PSR_MIXED;
   const bool fits = block_layout(g.mech, g.cond.energy, r.mixed, r.L);
   r.lds = (size_t)r.L.total * 8;
-  r.wplan = wave_plan(g.mech, g.cond.energy, r.mixed, o->engine);
+  r.wplan = wave_plan(g.mech, g.cond.energy, r.mixed, o->engine, o->rpw);
+  r.wplan.per_cu_cap = o->grid_per_cu;
   if (o->engine == 2 && !r.wplan.NP)
     return fail(PSR_EUNSUPPORTED, "wavefront engine needs n <= 64 and a mechanism that fits its LDS");
   if (!r.wplan.NP && !fits)
@@ -1176,7 +1185,7 @@ static psr_status launch_group(GroupRun &r, const psr_solve_opts *o, hipStream_t
     return run_wave(gd, od, r.wplan, mixed, o->scheduler, states, counters, area, stream, o->max_lin * 2 + 8,
                     &r.rounds, o->use_graph != 0);
   if (o->scheduler == PSR_PERSISTENT) {
-    const int64_t grid = block_grid(L, mixed, B);
+    const int64_t grid = block_grid(L, mixed, B, o->grid_per_cu);
     if (grid <= 0) return fail(PSR_EDEVICE, "occupancy query failed");
     double *matws = L.split ? area : nullptr;  // one HBM matrix area per resident workgroup
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, counters, 64);
@@ -1302,5 +1311,248 @@ extern "C" psr_status psr_solve_batch(const psr_group *groups, int32_t n_groups,
     if (st != PSR_OK) return st;
   }
   if (stats) stats->kernel_ms = ms;
+  return PSR_OK;
+}
+
+// ------------------------------------------------------------ host: autotuner
+
+namespace {
+
+// Device buffers of one group's sample: copies of the first S reactors' state
+// and inlet composition ([var][S]), and the sample's own status array.
+struct TuneSample {
+  psr_group g{};
+  double *x0 = nullptr, *x = nullptr, *Yin = nullptr;
+  int32_t *status = nullptr;
+  size_t xbytes = 0;
+};
+
+void free_samples(std::vector<TuneSample> &v) {
+  for (TuneSample &t : v) {
+    if (t.x0) (void)hipFree(t.x0);
+    if (t.x) (void)hipFree(t.x);
+    if (t.Yin) (void)hipFree(t.Yin);
+    if (t.status) (void)hipFree(t.status);
+    t = TuneSample{};
+  }
+}
+
+std::string tune_key(const psr_group *groups, int32_t n_groups, const psr_solve_opts *o, int64_t sample) {
+  int dev = 0, ncu = 0;
+  hipDeviceProp_t prop{};
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    arch = prop.gcnArchName;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 0;
+  for (char &ch : arch)
+    if (ch == ' ' || ch == '\t') ch = '_';
+  std::string k = arch + "/cu" + std::to_string(ncu) + "/p" + std::to_string(o->precision) + "/s" +
+                  std::to_string(o->scheduler);
+  for (int gi = 0; gi < n_groups; gi++) {
+    const psr_mech_t m = groups[gi].mech;
+    const int64_t S = std::min<int64_t>(sample, groups[gi].cond.n_reactors);
+    k += "/g" + std::to_string(m->N) + "," + std::to_string(m->I) + "," + std::to_string(m->nnz) + "," +
+         std::to_string(m->dev.soot ? 1 : 0) + "," + std::to_string(groups[gi].cond.energy ? 1 : 0) + "," +
+         std::to_string(S);
+  }
+  return k;
+}
+
+// Last line of the cache whose key matches; false when there is none.
+bool cache_lookup(const char *path, const std::string &key, psr_tune_result *r) {
+  FILE *f = fopen(path, "r");
+  if (!f) return false;
+  char line[2048], k[1024];
+  bool hit = false;
+  while (fgets(line, sizeof line, f)) {
+    psr_tune_result t{};
+    if (sscanf(line, "%1023s engine=%d rpw=%d grid_per_cu=%d ms=%lf solves_per_s=%lf", k, &t.engine, &t.rpw,
+               &t.grid_per_cu, &t.ms, &t.solves_per_s) == 6 &&
+        key == k && t.engine >= 0 && t.engine <= 2 && (t.rpw == 0 || t.rpw == 1 || t.rpw == 2 || t.rpw == 4) &&
+        t.grid_per_cu >= 0 && t.grid_per_cu <= 32) {
+      *r = t;
+      hit = true;
+    }
+  }
+  fclose(f);
+  return hit;
+}
+
+}  // namespace
+
+extern "C" psr_status psr_autotune(const psr_group *groups, int32_t n_groups, psr_solve_opts *opts, int64_t sample,
+                                   const char *cache_path, psr_tune_result *result, void *stream) {
+  psr_status st = check_opts(opts);
+  if (st != PSR_OK) return st;
+  if (!groups || n_groups <= 0) return fail(PSR_EINVAL, "no groups");
+  if (sample < 1) return fail(PSR_EINVAL, "sample must be >= 1");
+  for (int gi = 0; gi < n_groups; gi++) {
+    st = check_cond(groups[gi].mech, &groups[gi].cond);
+    if (st != PSR_OK) return st;
+    if (!groups[gi].x_inout) return fail(PSR_EINVAL, "null x_inout");
+  }
+  const std::string key = tune_key(groups, n_groups, opts, sample);
+  if (key.size() >= 1000) return fail(PSR_EINVAL, "too many groups for the autotune cache key");
+  psr_tune_result best{};
+  if (cache_path && cache_lookup(cache_path, key, &best)) {
+    best.candidates = 0;
+    best.default_ms = 0;
+    opts->engine = best.engine;
+    opts->rpw = best.rpw;
+    opts->grid_per_cu = best.grid_per_cu;
+    if (result) *result = best;
+    return PSR_OK;
+  }
+
+  // Candidate shapes.  The automatic shape comes first and wins ties within
+  // 2 %, so noise does not move the choice off it.
+  const bool mixed = opts->precision == PSR_MIXED;
+  bool any_wave = false;
+  for (int gi = 0; gi < n_groups; gi++)
+    any_wave |= wave_plan(groups[gi].mech, groups[gi].cond.energy, mixed, 0).NP != 0;
+  struct Shape { int engine, rpw, grid; };
+  std::vector<Shape> shapes;
+  std::vector<int> grids = {0};
+  if (opts->scheduler == PSR_PERSISTENT) grids = {0, 1, 2};
+  // rpw values whose plans on the wave groups repeat an earlier value's are
+  // not tried.
+  std::vector<int> rpws;
+  std::vector<std::vector<int>> seen;
+  for (int rpw : {0, 2, 1}) {
+    std::vector<int> eff;
+    for (int gi = 0; gi < n_groups; gi++)
+      eff.push_back(wave_plan(groups[gi].mech, groups[gi].cond.energy, mixed, 0, rpw).rpw);
+    if (std::find(seen.begin(), seen.end(), eff) != seen.end()) continue;
+    seen.push_back(eff);
+    rpws.push_back(rpw);
+  }
+  for (int gr : grids) {
+    for (int rpw : rpws) shapes.push_back({0, rpw, gr});
+    if (any_wave) shapes.push_back({1, 0, gr});
+  }
+
+  // Sample copies.
+  std::vector<TuneSample> smp(n_groups);
+  auto cleanup = [&]() { free_samples(smp); };
+  const hipStream_t cs = (hipStream_t)stream;
+#define TUNE_OK(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) {                                                               \
+      cleanup();                                                                          \
+      return fail(PSR_EDEVICE, std::string(#expr " failed: ") + hipGetErrorString(e_));   \
+    }                                                                                     \
+  } while (0)
+  TUNE_OK(hipStreamSynchronize(cs));
+  for (int gi = 0; gi < n_groups; gi++) {
+    const psr_group &src = groups[gi];
+    TuneSample &t = smp[gi];
+    const int64_t B = src.cond.n_reactors;
+    const int64_t S = std::min<int64_t>(sample, B);
+    const int n = n_unknowns(src.mech->dev, src.cond.energy);
+    const int N = src.mech->N;
+    t.xbytes = (size_t)n * S * 8;
+    TUNE_OK(hipMalloc(&t.x0, t.xbytes));
+    TUNE_OK(hipMalloc(&t.x, t.xbytes));
+    TUNE_OK(hipMalloc(&t.Yin, (size_t)N * S * 8));
+    TUNE_OK(hipMalloc(&t.status, (size_t)S * 4));
+    TUNE_OK(hipMemcpy2DAsync(t.x0, S * 8, src.x_inout, B * 8, S * 8, n, hipMemcpyDeviceToDevice, cs));
+    TUNE_OK(hipMemcpy2DAsync(t.Yin, S * 8, src.cond.Y_in, B * 8, S * 8, N, hipMemcpyDeviceToDevice, cs));
+    t.g.mech = src.mech;
+    t.g.cond = src.cond;  // P, tau, T_in: the first S entries of the caller's arrays
+    t.g.cond.n_reactors = S;
+    t.g.cond.Y_in = t.Yin;
+    t.g.x_inout = t.x;
+    t.g.status = t.status;
+    t.g.n_lin = nullptr;
+  }
+  TUNE_OK(hipStreamSynchronize(cs));
+  std::vector<psr_group> sg(n_groups);
+  for (int gi = 0; gi < n_groups; gi++) sg[gi] = smp[gi].g;
+
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  psr_status last = PSR_OK;
+  std::string last_err;
+  double best_score = -1;
+  bool have = false;
+  int timed = 0;
+  double default_ms = 0;
+  for (size_t ci = 0; ci < shapes.size(); ci++) {
+    psr_solve_opts o = *opts;
+    o.engine = shapes[ci].engine;
+    o.rpw = shapes[ci].rpw;
+    o.grid_per_cu = shapes[ci].grid;
+    const size_t need = psr_workspace_bytes(sg.data(), n_groups, &o);
+    if (need == 0) {
+      cleanup();
+      return fail(PSR_EINVAL, "psr_workspace_bytes failed for the sample");
+    }
+    if (need > ws_bytes) {
+      if (ws) (void)hipFree(ws);
+      ws = nullptr;
+      ws_bytes = 0;
+      hipError_t e = hipMalloc(&ws, need);
+      if (e != hipSuccess) {
+        cleanup();
+        return fail(PSR_ENOMEM, std::string("autotune workspace: ") + hipGetErrorString(e));
+      }
+      ws_bytes = need;
+    }
+    double ms = 1e300;
+    int64_t conv = 0;
+    psr_status rs = PSR_OK;
+    for (int rep = 0; rep < 3 && rs == PSR_OK; rep++) {
+      for (int gi = 0; gi < n_groups && rs == PSR_OK; gi++)
+        if (hipMemcpyAsync(smp[gi].x, smp[gi].x0, smp[gi].xbytes, hipMemcpyDeviceToDevice, cs) != hipSuccess)
+          rs = fail(PSR_EDEVICE, "autotune: restoring the sample state failed");
+      if (rs != PSR_OK) break;
+      psr_solve_stats stt{};
+      rs = psr_solve_batch(sg.data(), n_groups, &o, ws, ws_bytes, &stt, stream);
+      if (rs == PSR_OK && rep > 0) {  // the first run is untimed
+        ms = std::min(ms, stt.kernel_ms);
+        conv = stt.converged;
+      }
+    }
+    if (rs == PSR_EUNSUPPORTED || rs == PSR_EINVAL) {  // this shape does not apply here
+      last = rs;
+      last_err = g_err;
+      continue;
+    }
+    if (rs != PSR_OK) {
+      (void)hipFree(ws);
+      cleanup();
+      return rs;
+    }
+    timed++;
+    if (ci == 0) default_ms = ms;
+    const double score = (double)conv / (ms * 1e-3);
+    if (!have || score > best_score * 1.02) {
+      have = true;
+      best_score = score;
+      best.engine = o.engine;
+      best.rpw = o.rpw;
+      best.grid_per_cu = o.grid_per_cu;
+      best.ms = ms;
+      best.solves_per_s = score;
+    }
+  }
+  if (ws) (void)hipFree(ws);
+  cleanup();
+#undef TUNE_OK
+  if (!have) return fail(last == PSR_OK ? PSR_EINVAL : last, "autotune: no candidate shape ran: " + last_err);
+  best.candidates = timed;
+  best.default_ms = default_ms;
+  opts->engine = best.engine;
+  opts->rpw = best.rpw;
+  opts->grid_per_cu = best.grid_per_cu;
+  if (result) *result = best;
+  if (cache_path) {
+    FILE *f = fopen(cache_path, "a");
+    if (!f) return fail(PSR_EINVAL, std::string("autotune: cannot append to cache file ") + cache_path);
+    fprintf(f, "%s engine=%d rpw=%d grid_per_cu=%d ms=%.6f solves_per_s=%.3f\n", key.c_str(), best.engine,
+            best.rpw, best.grid_per_cu, best.ms, best.solves_per_s);
+    fclose(f);
+  }
   return PSR_OK;
 }

@@ -148,3 +148,25 @@ def test_rejects_bad_soot_description(lib):
         msg = lib.psr_last_error().decode()
         assert st == 1 and words in msg, (sd, msg)
     assert set(SOOT_CONSTANTS) <= set(good)
+
+
+def test_launch_shape_options_are_validated_on_the_host(lib):
+    """rpw outside {0, 1, 2, 4} or grid_per_cu outside 0..32 is rejected
+    before any device work, by both the solve and the autotuner."""
+    from paper_2005_11468_amd import _lib
+    g = (_lib.Group * 1)()
+    res = _lib.TuneResult()
+    for bad in (dict(rpw=3), dict(rpw=8), dict(grid_per_cu=-1), dict(grid_per_cu=33)):
+        o = _lib.SolveOpts()
+        lib.psr_default_opts(C.byref(o))
+        assert o.rpw == 0 and o.grid_per_cu == 0
+        for k, v in bad.items():
+            setattr(o, k, v)
+        assert lib.psr_solve_batch(g, 1, C.byref(o), None, 0, None, None) == _lib.PSR_EINVAL
+        assert lib.psr_autotune(g, 1, C.byref(o), 16, None, C.byref(res), None) == _lib.PSR_EINVAL
+        assert b"option out of range" in lib.psr_last_error()
+    o = _lib.SolveOpts()
+    lib.psr_default_opts(C.byref(o))
+    assert lib.psr_autotune(g, 1, C.byref(o), 0, None, C.byref(res), None) == _lib.PSR_EINVAL
+    assert b"sample" in lib.psr_last_error()
+    assert lib.psr_autotune(g, 0, C.byref(o), 16, None, C.byref(res), None) == _lib.PSR_EINVAL
