@@ -91,6 +91,94 @@ def rate_kernel(P, B, steps=5):
             "frac_hbm": gbs / PEAK_HBM_GBS, "finite": ok}
 
 
+def newton_sweep(P, sizes, steps=3):
+    """One Newton iteration per reactor (residual, analytic Jacobian, FP64 LU
+    factorisation, triangular solves) on the 101/542 mechanism at the paper's
+    single-iteration conditions (isothermal 1800 K, tau = 50 ms, inlet
+    0.15/0.18/0.67 fuel/oxidizer/diluent, every reactor alike), at each batch
+    size; 'rate_jac' times the residual and Jacobian alone.  The oracle's
+    single-thread rate for the same iteration is measured on 20 reactors."""
+    import ctypes as C
+    import torch
+    from psr_inputs import workload
+    from paper_2005_11468_amd import _lib
+    mech, cond, x0, energy = workload("newton101", 1)
+    M = P.Mechanism(mech)
+    N, I = mech["species_elems"].shape[0], mech["A"].shape[0]
+    n = x0.shape[0]
+    nnz = int(sum(len(set(int(v) for v in list(mech["reac_idx"][k]) + list(mech["prod_idx"][k]) if v >= 0))
+                  for k in range(I)))
+    res_fl, _ = residual_work(N, I, nnz, n)
+    it_fl = res_fl + 54.0 * I + 2.0 * n * n + 2.0 / 3.0 * n ** 3 + 2.0 * n * n
+    L = _lib.load()
+    stream = torch.cuda.current_stream()
+    sp = C.c_void_p(stream.cuda_stream)
+    out = {"mechanism": f"{N} species / {I} reactions, isothermal 1800 K, tau 50 ms",
+           "flops_per_iteration": it_fl, "sizes": []}
+    for B in sizes:
+        d = "cuda:0"
+        cd = {"P": torch.full((B,), float(cond["P"][0]), dtype=torch.float64, device=d),
+              "tau": torch.full((B,), float(cond["tau"][0]), dtype=torch.float64, device=d),
+              "T_in": torch.full((B,), float(cond["T_in"][0]), dtype=torch.float64, device=d),
+              "Y_in": torch.from_numpy(cond["Y_in"]).to(d).expand(N, B).contiguous()}
+        x = cd["Y_in"].clone()
+        F = torch.empty_like(x)
+        J = torch.empty((B, n, n), dtype=torch.float64, device=d)
+        piv = torch.empty((B, n), dtype=torch.int32, device=d)
+        info = torch.empty((B,), dtype=torch.int32, device=d)
+        rhs = torch.empty((B, n), dtype=torch.float64, device=d)
+
+        def rate_jac():
+            P.residual(M, cd, energy, x, F, stream=stream)
+            P.jacobian(M, cd, energy, x, J, stream=stream)
+
+        def iteration():
+            rate_jac()
+            _lib.check(L.psr_lu_factor_batch(n, B, P.PSR_FP64, C.c_void_p(J.data_ptr()),
+                                             C.c_void_p(piv.data_ptr()), C.c_void_p(info.data_ptr()), sp),
+                       "psr_lu_factor_batch")
+            torch.neg(F.t(), out=rhs)
+            _lib.check(L.psr_lu_solve_batch(n, B, C.c_void_p(J.data_ptr()), C.c_void_p(piv.data_ptr()),
+                                            C.c_void_p(rhs.data_ptr()), sp), "psr_lu_solve_batch")
+
+        row = {"reactors": B}
+        for name, fn in (("rate_jac", rate_jac), ("iteration", iteration)):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            row[name] = {"ms": ms, "reactor_evals_per_s": B / (ms / 1e3)}
+        row["iteration"]["achieved_tflops"] = it_fl * B / (row["iteration"]["ms"] / 1e3) / 1e12
+        row["nonsingular"] = int((info == 0).sum().item())
+        row["finite"] = bool(torch.isfinite(rhs).all().item())
+        out["sizes"].append(row)
+        print(f"newton101 B={B}: {row['iteration']['ms']:.3f} ms per iteration", file=sys.stderr, flush=True)
+        del cd, x, F, J, piv, info, rhs
+        torch.cuda.empty_cache()
+    try:
+        from oracle import oracle as O
+        om = O.Mechanism(mech)
+        args = (cond["P"][0], cond["tau"][0], cond["T_in"][0], cond["Y_in"][:, 0], energy, x0[:, 0])
+        t0 = time.perf_counter()
+        reps = 20
+        for _ in range(reps):
+            Fo = om.residual(*args)
+            Jo = om.jacobian(*args)
+            lo, po, io = O.lu_factor(Jo)
+            O.lu_solve(lo, po, -Fo)
+        t = time.perf_counter() - t0
+        out["cpu_oracle"] = {"reactor_evals_per_s": reps / t, "cores": 1, "kind": "oracle",
+                             "sample": f"{reps} reactor-iterations, single-threaded FP64 C oracle"}
+    except Exception as e:  # the oracle is a reported baseline only
+        out["cpu_oracle"] = {"error": str(e)}
+    return out
+
+
 def lu_large(P, n=201, B=9830, steps=3):
     """psr_lu_factor_batch with float factors on B seeded random n x n
     matrices (the 200/1200 mechanism's matrix size and reactor count of the
@@ -202,6 +290,8 @@ def main():
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--soot-reactors", type=int, default=512,
                     help="prefix of the sooting workload to solve (0: skip)")
+    ap.add_argument("--newton-sizes", default="100,1000,10000,100000,1000000",
+                    help="batch sizes of the one-Newton-iteration sweep, comma separated ('' or 0: skip)")
     ap.add_argument("--tune-sample", type=int, default=4096,
                     help="reactors the autotuner times each launch shape on (0: automatic shape)")
     ap.add_argument("--rate-reactors", type=int, default=1_000_000,
@@ -284,6 +374,8 @@ def main():
     lu_big = lu_large(P) if not args.no_lu_large else None
     unev = uneven(P) if not args.no_uneven else None
     soot_leg = soot(P, args.soot_reactors) if args.soot_reactors > 0 else None
+    sizes = [int(v) for v in args.newton_sizes.split(",") if v.strip() and int(v) > 0]
+    newton = newton_sweep(P, sizes) if sizes else None
 
     # oracle on a bounded sample: CPU baseline and parity reference
     cpu = None
@@ -353,6 +445,7 @@ def main():
         "lu_large": lu_big,
         "uneven": unev,
         "soot": soot_leg,
+        "newton101": newton,
         "parity": parity,
         "cpu_baseline": cpu,
     }

@@ -13,6 +13,9 @@ Recipes (see also the workload table in psr_inputs.configs):
   paper's speed-up runs use 0.67 N2, Section 6), the rest split as
   X_F = 0.33 phi/(1+phi), X_O = 0.33/(1+phi) with phi ~ U[phi_lo, phi_hi],
   converted to mass fractions with the species weights.
+* "fod": fixed fuel/oxidizer/diluent mole fractions 0.15/0.18/0.67 (the
+  inlet of the paper's single-iteration speed-up runs, Section 6), T fixed
+  (given as T_in); every reactor gets the same inlet.
 """
 from __future__ import annotations
 
@@ -45,6 +48,13 @@ def make_conditions(mech: dict, n_reactors: int, seed: int, *, recipe: str,
         mass = X * W[:, None]
         Y = mass / mass.sum(axis=0, keepdims=True)
         Tin = rng.uniform(T_in_range[0], T_in_range[1], B)
+    elif recipe == "fod":
+        W = species_weights(mech)
+        X = np.zeros(n_sp)
+        X[mech["fuel"]], X[mech["oxidizer"]], X[mech["diluent"]] = 0.15, 0.18, 0.67
+        y = X * W / (X * W).sum()
+        Y = np.repeat(y[:, None], B, axis=1)
+        Tin = np.full(B, float(T_in if T_in is not None else 1800.0))
     else:
         raise ValueError(f"unknown recipe {recipe!r}")
     return {

@@ -35,6 +35,9 @@ MECH_SPECS = {
     "uneven_b": (100, 600, 49),
     "uneven_c": (200, 1200, 43),
     "soot": (150, 900, 56),
+    # stand-in for the 101-species / 542-reaction mechanism of the paper's
+    # single-Newton-iteration speed-up measurement (Section 6)
+    "newton101": (101, 542, 71),
 }
 
 # Soot model constants of the sooting workload (fixed, not drawn): nucleation
@@ -61,6 +64,10 @@ WORKLOADS = {
     # residual-kernel throughput batch (the paper's largest batch size, 1e6)
     "rate": dict(mech="mixed", B=1_000_000, seed=62, energy=True, recipe="phi",
                  tau_range=(1e-5, 1e-1)),
+    # one Newton iteration per reactor at the paper's speed-up conditions:
+    # isothermal 1800 K, tau = 50 ms, fuel/oxidizer/diluent 0.15/0.18/0.67
+    "newton101": dict(mech="newton101", B=100, seed=72, energy=False, recipe="fod",
+                      tau_range=(0.05, 0.05), T_in=1800.0),
     # sooting reactors: fuel-rich inlet (the paper's sooting case has
     # equivalence ratio 2.5) and 6 soot moments per reactor
     "soot": dict(mech="soot", B=8192, seed=52, energy=True, recipe="phi",
