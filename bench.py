@@ -55,13 +55,14 @@ def alg_flops(n, N, I):
     return lin, rnd
 
 
-def rate_kernel(P, B, steps=5):
-    """psr_residual over B reactors of the 53/325 mechanism (inputs resident in
-    HBM), timed with HIP events on the launch stream."""
+def rate_kernel(P, B, steps=5, name="rate"):
+    """psr_residual over B reactors of the 53/325 mechanism ('rate') or the
+    200/1200 one ('rate200'), inputs resident in HBM, timed with HIP events on
+    the launch stream."""
     import torch
     from psr_inputs import workload
     from tests.gpu_util import cond_dev, dev
-    mech, cond, x0, energy = workload("rate", B)
+    mech, cond, x0, energy = workload(name, B)
     M = P.Mechanism(mech)
     cd = cond_dev(cond)
     xd = dev(x0)
@@ -84,7 +85,8 @@ def rate_kernel(P, B, steps=5):
     tf = fl * B / (ms / 1e3) / 1e12
     gbs = by * B / (ms / 1e3) / 1e9
     ok = bool(torch.isfinite(F).all().item())
-    return {"kernel": "k_wresidual", "reactors": B, "ms_per_launch": ms,
+    return {"kernel": "k_wresidual" if x0.shape[0] <= 64 else "k_residual",
+            "mechanism": f"{N} species / {I} reactions", "reactors": B, "ms_per_launch": ms,
             "reactor_evals_per_s": B / (ms / 1e3), "flops_per_reactor": fl,
             "bytes_per_reactor": by, "achieved_tflops": tf, "peak_tflops": PEAK_ALU_TFLOPS,
             "frac_fp64": tf / PEAK_ALU_TFLOPS, "achieved_gbs": gbs, "peak_gbs": PEAK_HBM_GBS,
@@ -368,9 +370,10 @@ def main():
     ms_fp64p, _, st_fp64p, _ = run(fp64p, args.plain_steps, 0)
     s_fp64p = status.cpu().numpy()
 
-    rate = None
+    rate = rate200 = None
     if args.rate_reactors > 0:
         rate = rate_kernel(P, args.rate_reactors)
+        rate200 = rate_kernel(P, args.rate_reactors, name="rate200")
     lu_big = lu_large(P) if not args.no_lu_large else None
     unev = uneven(P) if not args.no_uneven else None
     soot_leg = soot(P, args.soot_reactors) if args.soot_reactors > 0 else None
@@ -442,6 +445,7 @@ def main():
                      "kernel_ms": st_mixed.kernel_ms,
                      "alg_flops": flops},
         "rate_kernel": rate,
+        "rate_kernel_200sp": rate200,
         "lu_large": lu_big,
         "uneven": unev,
         "soot": soot_leg,

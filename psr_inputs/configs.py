@@ -64,6 +64,8 @@ WORKLOADS = {
     # residual-kernel throughput batch (the paper's largest batch size, 1e6)
     "rate": dict(mech="mixed", B=1_000_000, seed=62, energy=True, recipe="phi",
                  tau_range=(1e-5, 1e-1)),
+    "rate200": dict(mech="uneven_c", B=1_000_000, seed=63, energy=True, recipe="phi",
+                    tau_range=(1e-6, 1.0)),
     # one Newton iteration per reactor at the paper's speed-up conditions:
     # isothermal 1800 K, tau = 50 ms, fuel/oxidizer/diluent 0.15/0.18/0.67
     "newton101": dict(mech="newton101", B=100, seed=72, energy=False, recipe="fod",
