@@ -1485,6 +1485,7 @@ extern "C" psr_status psr_autotune(const psr_group *groups, int32_t n_groups, ps
     o.grid_per_cu = shapes[ci].grid;
     const size_t need = psr_workspace_bytes(sg.data(), n_groups, &o);
     if (need == 0) {
+      if (ws) (void)hipFree(ws);
       cleanup();
       return fail(PSR_EINVAL, "psr_workspace_bytes failed for the sample");
     }
