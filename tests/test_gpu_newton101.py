@@ -87,7 +87,10 @@ def test_newton_iteration_at_scale_sampled(gpu, oracle_mod):
     match the oracle."""
     from psr_inputs import workload
     B = 100_000
-    mech, cond, x0, _ = workload("newton101", B)
+    mech, cond1, _, _ = workload("newton101", 1)  # every reactor of the workload is alike
+    cond = {k: np.ascontiguousarray(np.repeat(v[..., :1], B, axis=-1)) for k, v in cond1.items()}
+    x0 = cond["Y_in"].copy()
+    assert x0.shape == (101, B) and cond["P"].shape == (B,)
     M = gpu.Mechanism(mech)
     O = oracle_mod.Mechanism(mech)
     F, J, info, d = _newton_step_gpu(gpu, M, cond, x0)
