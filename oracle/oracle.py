@@ -312,3 +312,23 @@ def solve_batch(mech: dict, cond: dict, x0: np.ndarray, energy: bool, *, idx=Non
              "n_jac": st[:, 2].astype(int), "n_ts": st[:, 3].astype(int),
              "n_attempts": st[:, 4].astype(int), "sres": st[:, 5]}
     return xs, stats
+
+
+def sweep_batch(mech: dict, cond: dict, x0: np.ndarray, energy: bool, param: str,
+                values: np.ndarray, *, opts: Opts | None = None, processes: int = 1):
+    """Continuation sweep (paper Section 4: steady solutions followed along
+    one condition, each started from the solution before).  At step k the
+    condition `param` ("T_in" or "tau") of reactor b is values[k, b]; the
+    initial guess of step k is the state step k-1 left (x0 at step 0).
+    Returns (x [n_steps][n][B], status [n_steps][B])."""
+    if param not in ("T_in", "tau"):
+        raise ValueError(param)
+    x = np.array(x0, dtype=np.float64, copy=True)
+    xs, sts = [], []
+    for row in np.asarray(values, dtype=np.float64):
+        c = dict(cond)
+        c[param] = np.ascontiguousarray(row)
+        x, st = solve_batch(mech, c, x, energy, opts=opts, processes=processes)
+        xs.append(x.copy())
+        sts.append(st["status"])
+    return np.stack(xs), np.stack(sts)

@@ -130,3 +130,30 @@ def subset(cond: dict, x0: np.ndarray, idx) -> tuple[dict, np.ndarray]:
     idx = np.asarray(idx)
     return ({k: np.ascontiguousarray(v[..., idx]) for k, v in cond.items()},
             np.ascontiguousarray(x0[:, idx]))
+
+
+# Continuation sweeps of the paper's validation protocol (Section 4), run on
+# isothermal reactors of the 53-species mechanism with the phi inlet:
+# temperature 1500 -> 2000 K in 50 K steps at tau = 5 ms, and residence time
+# 5 -> 95 ms in 5 ms steps at 1750 K.  Every reactor of the batch is its own
+# chain (its own equivalence ratio); the swept condition is the same for all.
+SWEEPS = {
+    "T_in": dict(values=np.arange(1500.0, 2000.0 + 1e-9, 50.0), fixed=("tau", 5e-3)),
+    "tau": dict(values=np.arange(5e-3, 95e-3 + 1e-12, 5e-3), fixed=("T_in", 1750.0)),
+}
+
+
+def sweep_workload(param: str, n_chains: int, seed: int = 82, mech_name: str = "mixed"):
+    """(mechanism, conditions, x0, values [n_steps][B]) of a continuation
+    sweep over `param` ("T_in" or "tau"); the conditions hold the fixed
+    condition and the first step's value of the swept one, x0 is the inlet."""
+    spec = SWEEPS[param]
+    mech = mechanism(mech_name)
+    B = int(n_chains)
+    cond = make_conditions(mech, B, seed, recipe="phi")
+    other, val = spec["fixed"]
+    cond[other] = np.full(B, float(val))
+    steps = np.asarray(spec["values"], dtype=np.float64)
+    values = np.ascontiguousarray(np.repeat(steps[:, None], B, axis=1))
+    cond[param] = values[0].copy()
+    return mech, cond, initial_guess(cond, False), values
