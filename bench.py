@@ -278,6 +278,37 @@ def soot(P, reactors=512):
     return out
 
 
+def continuation(P, chains=4096):
+    """The paper's continuation protocol (temperature 1500 -> 2000 K at 5 ms,
+    then residence time 5 -> 95 ms at 1750 K, each step warm-started from the
+    one before) on isothermal reactors of the 53-species mechanism, every
+    reactor its own chain: mixed-precision persistent psr_sweep_batch."""
+    import torch
+    from psr_inputs.configs import sweep_workload
+    from tests.gpu_util import cond_dev, dev
+    out = {"chains": chains}
+    o = P.default_opts(precision=P.PSR_MIXED, scheduler=P.PSR_PERSISTENT)
+    for param in ("T_in", "tau"):
+        mech, cond, x0, values = sweep_workload(param, chains)
+        M = P.Mechanism(mech)
+        x0d, vd = dev(x0), dev(values)
+        g = dict(mech=M, cond=cond_dev(cond), energy=False, x=x0d.clone(),
+                 status=torch.empty(chains, dtype=torch.int32, device="cuda:0"))
+        _, xp, sp, ws = P.sweep_batch(g, param, vd, o)  # warm-up (same inputs)
+        g["x"].copy_(x0d)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, xp, sp, _ = P.sweep_batch(g, param, vd, o, workspace=ws, x_path=xp, status_path=sp)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[param] = {"steps": int(values.shape[0]), "converged": int(st.converged),
+                      "reactor_solves": int(st.reactors), "kernel_ms": st.kernel_ms, "wall_ms": wall * 1e3,
+                      "converged_per_s": st.converged / wall}
+        print(f"sweep {param}: {st.converged}/{st.reactors} converged in {wall * 1e3:.1f} ms",
+              file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -290,6 +321,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lu-large", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
+    ap.add_argument("--sweep-chains", type=int, default=4096,
+                    help="chains of the continuation sweeps (0: skip)")
     ap.add_argument("--soot-reactors", type=int, default=512,
                     help="prefix of the sooting workload to solve (0: skip)")
     ap.add_argument("--newton-sizes", default="100,1000,10000,100000,1000000",
@@ -379,6 +412,7 @@ def main():
     soot_leg = soot(P, args.soot_reactors) if args.soot_reactors > 0 else None
     sizes = [int(v) for v in args.newton_sizes.split(",") if v.strip() and int(v) > 0]
     newton = newton_sweep(P, sizes) if sizes else None
+    sweep_leg = continuation(P, args.sweep_chains) if args.sweep_chains > 0 else None
 
     # oracle on a bounded sample: CPU baseline and parity reference
     cpu = None
@@ -450,6 +484,7 @@ def main():
         "uneven": unev,
         "soot": soot_leg,
         "newton101": newton,
+        "continuation": sweep_leg,
         "parity": parity,
         "cpu_baseline": cpu,
     }

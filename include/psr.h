@@ -243,6 +243,33 @@ psr_status psr_solve_batch(const psr_group *groups, int32_t n_groups, const psr_
                            void *workspace, size_t workspace_bytes, psr_solve_stats *stats,
                            void *stream);
 
+/* Parameter a continuation sweep varies. */
+enum { PSR_SWEEP_T_IN = 0, PSR_SWEEP_TAU = 1 };
+
+/* Continuation sweep (paper Section 4: steady solutions followed along the
+ * reactor temperature at a fixed residence time, and along the residence
+ * time at a fixed temperature, each solution started from the one before).
+ * group: one mechanism's B reactors, each the start of its own chain.  At
+ * step k = 0..n_steps-1 the condition named by `param` (T_in, which for
+ * isothermal reactors is the reactor temperature, or tau) is taken from
+ * values + k*B (device, [n_steps][B] float64); the group's own pointer for
+ * that condition is ignored and may be NULL.  group->x_inout holds the
+ * initial guess of step 0 and, on return, the state the last step left;
+ * every step starts from the state the step before left, whether or not
+ * that reactor converged there (status_path says).  x_path (device
+ * [n_steps][n][B], may be NULL) and status_path (device [n_steps][B], may
+ * be NULL) receive each step's state and status; group->status and
+ * group->n_lin hold the last step's.  workspace: at least
+ * psr_workspace_bytes() of the group (the same at every step).  stats (host,
+ * optional): reactors, converged, lin_total, jac_total, fp64_fallbacks,
+ * rounds and kernel_ms summed over the steps, lin_max the largest.  Blocks
+ * until the last step is complete on `stream`.  Errors: PSR_EINVAL for a
+ * bad param, n_steps < 1 or a null `values`, else those of psr_solve_batch
+ * (the sweep stops at the failing step). */
+psr_status psr_sweep_batch(const psr_group *group, int32_t param, int32_t n_steps, const double *values,
+                           const psr_solve_opts *opts, void *workspace, size_t workspace_bytes,
+                           double *x_path, int32_t *status_path, psr_solve_stats *stats, void *stream);
+
 /* Outcome of psr_autotune. */
 typedef struct {
   int32_t engine, rpw, grid_per_cu; /* the chosen launch shape (as in opts)       */

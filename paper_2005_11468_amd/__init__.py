@@ -202,6 +202,55 @@ def solve_batch(groups, opts: SolveOpts | None = None, workspace=None, stats: bo
     return st, workspace
 
 
+SWEEP_PARAMS = {"T_in": 0, "tau": 1}  # PSR_SWEEP_T_IN, PSR_SWEEP_TAU
+
+
+def sweep_batch(group, param: str, values, opts: SolveOpts | None = None, workspace=None,
+                x_path=None, status_path=None, stats: bool = True, stream=None):
+    """psr_sweep_batch: a continuation sweep of one group.  param "T_in" or
+    "tau"; values: [n_steps][B] float64 device tensor of that condition per
+    step (group["cond"] may omit it).  group["x"] holds the initial guess and
+    ends with the last step's state.  Returns (SolveStats or None, x_path
+    [n_steps][n][B], status_path [n_steps][B], workspace)."""
+    torch = _torch()
+    if param not in SWEEP_PARAMS:
+        raise ValueError(f"param must be one of {sorted(SWEEP_PARAMS)}")
+    values = _dev_f64(values, "values")
+    if values.dim() != 2:
+        raise ValueError("values must be [n_steps][B]")
+    opts = opts or default_opts()
+    g = dict(group)
+    cond = dict(g["cond"])
+    cond.setdefault(param, values[0])
+    g["cond"] = cond
+    G = _Groups([g])
+    B = G.arr[0].cond.n_reactors
+    if values.shape[1] != B:
+        raise ValueError(f"values has {values.shape[1]} reactors, the group {B}")
+    steps = values.shape[0]
+    n = g["mech"].n_unknowns(g["energy"])
+    dev = g["x"].device
+    if x_path is None:
+        x_path = torch.empty((steps, n, B), dtype=torch.float64, device=dev)
+    if status_path is None:
+        status_path = torch.empty((steps, B), dtype=torch.int32, device=dev)
+    if tuple(x_path.shape) != (steps, n, B) or x_path.dtype != torch.float64 or not x_path.is_contiguous():
+        raise ValueError("x_path must be a contiguous float64 [n_steps][n][B] tensor")
+    if tuple(status_path.shape) != (steps, B) or status_path.dtype != torch.int32 \
+            or not status_path.is_contiguous():
+        raise ValueError("status_path must be a contiguous int32 [n_steps][B] tensor")
+    L = _lib.load()
+    need = int(L.psr_workspace_bytes(G.arr, G.n, C.byref(opts)))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty((max(need, 1),), dtype=torch.uint8, device=dev)
+    st = SolveStats() if stats else None
+    r = L.psr_sweep_batch(G.arr, SWEEP_PARAMS[param], steps, _ptr(values), C.byref(opts),
+                          _ptr(workspace), workspace.numel(), _ptr(x_path), _ptr(status_path),
+                          C.byref(st) if st is not None else None, _stream(stream))
+    _lib.check(r, "psr_sweep_batch")
+    return st, x_path, status_path, workspace
+
+
 def autotune(groups, opts: SolveOpts, sample: int = 4096, cache_path: str | None = None, stream=None):
     """psr_autotune: times candidate launch shapes on the first `sample`
     reactors of each group (on copies) and writes the fastest into opts

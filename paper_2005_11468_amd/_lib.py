@@ -81,6 +81,8 @@ SYMBOLS = {
                          C.POINTER(SolveStats), vp], C.c_int),
     "psr_autotune": ([C.POINTER(Group), C.c_int32, C.POINTER(SolveOpts), C.c_int64, C.c_char_p,
                       C.POINTER(TuneResult), vp], C.c_int),
+    "psr_sweep_batch": ([C.POINTER(Group), C.c_int32, C.c_int32, vp, C.POINTER(SolveOpts), vp,
+                         C.c_size_t, vp, vp, C.POINTER(SolveStats), vp], C.c_int),
     "psr_last_error": ([], C.c_char_p),
 }
 

@@ -1314,6 +1314,55 @@ extern "C" psr_status psr_solve_batch(const psr_group *groups, int32_t n_groups,
   return PSR_OK;
 }
 
+// ------------------------------------------------------------ host: continuation sweep
+
+// Each step is one batched solve whose swept condition points at that step's
+// row of `values` and whose initial guess is the state the previous step left
+// in x_inout (the warm start of a continuation).  The state and status after
+// each step are copied out on the same stream before the next solve starts.
+extern "C" psr_status psr_sweep_batch(const psr_group *group, int32_t param, int32_t n_steps,
+                                      const double *values, const psr_solve_opts *opts, void *workspace,
+                                      size_t workspace_bytes, double *x_path, int32_t *status_path,
+                                      psr_solve_stats *stats, void *stream) {
+  if (!group) return fail(PSR_EINVAL, "null group");
+  if (param != PSR_SWEEP_T_IN && param != PSR_SWEEP_TAU) return fail(PSR_EINVAL, "unknown sweep parameter");
+  if (n_steps < 1) return fail(PSR_EINVAL, "n_steps must be >= 1");
+  if (!values) return fail(PSR_EINVAL, "null values");
+  if (!group->mech) return fail(PSR_EINVAL, "null mechanism");
+  const hipStream_t cs = (hipStream_t)stream;
+  const int64_t B = group->cond.n_reactors;
+  if (B <= 0) return fail(PSR_EINVAL, "n_reactors must be positive");
+  const int64_t n = psr_num_unknowns(group->mech, group->cond.energy);
+  psr_group g = *group;
+  psr_solve_stats total{}, one{};
+  for (int32_t k = 0; k < n_steps; k++) {
+    const double *row = values + (size_t)k * (size_t)B;
+    if (param == PSR_SWEEP_T_IN) g.cond.T_in = row;
+    else g.cond.tau = row;
+    psr_status st = psr_solve_batch(&g, 1, opts, workspace, workspace_bytes, stats ? &one : nullptr, stream);
+    if (st != PSR_OK) return st;
+    if (x_path)
+      HIP_OK(hipMemcpyAsync(x_path + (size_t)k * (size_t)(n * B), g.x_inout, sizeof(double) * (size_t)(n * B),
+                            hipMemcpyDeviceToDevice, cs));
+    if (status_path)
+      HIP_OK(hipMemcpyAsync(status_path + (size_t)k * (size_t)B, g.status, sizeof(int32_t) * (size_t)B,
+                            hipMemcpyDeviceToDevice, cs));
+    if (stats) {
+      total.reactors += one.reactors;
+      total.converged += one.converged;
+      total.lin_total += one.lin_total;
+      total.lin_max = std::max(total.lin_max, one.lin_max);
+      total.jac_total += one.jac_total;
+      total.fp64_fallbacks += one.fp64_fallbacks;
+      total.rounds += one.rounds;
+      total.kernel_ms += one.kernel_ms;
+    }
+  }
+  HIP_OK(hipStreamSynchronize(cs));
+  if (stats) *stats = total;
+  return PSR_OK;
+}
+
 // ------------------------------------------------------------ host: autotuner
 
 namespace {

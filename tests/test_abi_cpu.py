@@ -170,3 +170,19 @@ def test_launch_shape_options_are_validated_on_the_host(lib):
     assert lib.psr_autotune(g, 1, C.byref(o), 0, None, C.byref(res), None) == _lib.PSR_EINVAL
     assert b"sample" in lib.psr_last_error()
     assert lib.psr_autotune(g, 0, C.byref(o), 16, None, C.byref(res), None) == _lib.PSR_EINVAL
+
+
+def test_sweep_arguments_are_validated_on_the_host(lib):
+    """psr_sweep_batch rejects a null group, an unknown parameter, fewer
+    than one step and null values before any device work."""
+    from paper_2005_11468_amd import _lib
+    g = (_lib.Group * 1)()
+    o = _lib.SolveOpts()
+    lib.psr_default_opts(C.byref(o))
+    v = (C.c_double * 4)()
+    cases = [(None, 0, 1, v, "null group"), (g, 2, 1, v, "parameter"), (g, -1, 1, v, "parameter"),
+             (g, 0, 0, v, "n_steps"), (g, 1, 1, None, "null values"), (g, 0, 1, v, "mechanism")]
+    for grp, param, steps, vals, words in cases:
+        st = lib.psr_sweep_batch(grp, param, steps, C.cast(vals, C.c_void_p) if vals else None,
+                                 C.byref(o), None, 0, None, None, None, None)
+        assert st == _lib.PSR_EINVAL and words in lib.psr_last_error().decode(), words
