@@ -206,6 +206,24 @@ class Mechanism:
         fn(C.byref(self.s), C.byref(c), _dp(x), _dp(J))
         return J
 
+    def jacobian_fd(self, P, tau, T_in, Y_in, energy, x):
+        """Forward-difference Jacobian, the paper's route (Section 1): column j
+        is (F(x + h_j e_j) - F(x)) / h_j, n + 1 residual evaluations.  Step:
+        h_j = (x_j + d_j) - x_j with d_j = 2^-26 max(|x_j|, f_j), f_j = 1e-10
+        for species rows and 1 for the temperature and ln M_r rows."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        n = self.n_unknowns(energy)
+        F0 = self.residual(P, tau, T_in, Y_in, energy, x)
+        J = np.zeros((n, n))
+        for j in range(n):
+            floor = 1e-10 if j < self.n_sp else 1.0
+            d = 2.0 ** -26 * max(abs(x[j]), floor)
+            h = (x[j] + d) - x[j]
+            xp = x.copy()
+            xp[j] = x[j] + h
+            J[:, j] = (self.residual(P, tau, T_in, Y_in, energy, xp) - F0) / h
+        return J
+
     def mass_diag(self, P, tau, T_in, Y_in, energy, x):
         c, keep = self._cond(P, tau, T_in, Y_in, energy)
         x = np.ascontiguousarray(x, dtype=np.float64)
