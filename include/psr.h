@@ -143,6 +143,17 @@ psr_status psr_residual(psr_mech_t mech, const psr_conditions *cond, const doubl
 psr_status psr_jacobian(psr_mech_t mech, const psr_conditions *cond, const double *x, double *J,
                         void *stream);
 
+/* Finite-difference Jacobian, the route the paper takes (Section 1): n + 1
+ * residual evaluations per reactor, column j = (F(x + h_j e_j) - F(x)) / h_j
+ * with h_j = (x_j + d_j) - x_j, d_j = 2^-26 max(|x_j|, f_j), f_j = 1e-10 for
+ * the species rows and 1 for the temperature and ln M_r rows.  x: device
+ * [n][B]; J: device [B][n][n] as in psr_jacobian; work: device scratch of
+ * 3 n B doubles owned by the caller (F(x), F of the perturbed state, the
+ * perturbed state), contents undefined on return.  Asynchronous on
+ * `stream`; errors as psr_residual, PSR_EINVAL for a null x, J or work. */
+psr_status psr_jacobian_fd(psr_mech_t mech, const psr_conditions *cond, const double *x, double *J,
+                           double *work, void *stream);
+
 /* Batched LU with partial pivoting of B independent n x n row-major
  * matrices (device [B][n][n], overwritten by L\U with unit-lower L), pivots
  * device [B][n] (LAPACK convention: row k was swapped with row piv[k]),

@@ -128,6 +128,26 @@ def jacobian(mech: Mechanism, cond: dict, energy: bool, x, J=None, stream=None):
     return J
 
 
+def jacobian_fd(mech: Mechanism, cond: dict, energy: bool, x, J=None, work=None, stream=None):
+    """psr_jacobian_fd: forward-difference dF/dx from n + 1 residual
+    evaluations, [B][n][n] row-major per reactor.  work: float64 device
+    scratch of at least 3 n B elements (allocated when None)."""
+    torch = _torch()
+    c = _conditions(cond, energy)
+    x = _dev_f64(x, "x")
+    _check_state(mech, energy, x, c.n_reactors)
+    n, B = x.shape
+    if J is None:
+        J = torch.empty((B, n, n), dtype=torch.float64, device=x.device)
+    if work is None:
+        work = torch.empty((3 * n * B,), dtype=torch.float64, device=x.device)
+    if work.dtype != torch.float64 or not work.is_contiguous() or work.numel() < 3 * n * B:
+        raise ValueError("work must be a contiguous float64 tensor of at least 3 n B elements")
+    _lib.check(_lib.load().psr_jacobian_fd(mech.handle, C.byref(c), _ptr(x), _ptr(J), _ptr(work),
+                                           _stream(stream)), "psr_jacobian_fd")
+    return J
+
+
 def lu_factor_batch(A, precision=PSR_FP64, stream=None):
     """psr_lu_factor_batch on a [B][n][n] float64 tensor (in place).  Returns (A, piv, info)."""
     torch = _torch()

@@ -825,6 +825,79 @@ extern "C" psr_status psr_jacobian(psr_mech_t m, const psr_conditions *c, const 
   return PSR_OK;
 }
 
+// ------------------------------------------------------------ finite-difference Jacobian
+
+namespace fd {
+
+constexpr double kRel = 1.4901161193847656e-08;  // 2^-26, about the square root of FP64 epsilon
+constexpr double kFloorY = 1e-10;                // smallest |x_j| the step is scaled by (species rows)
+constexpr int kThreads = 256;
+
+// Forward-difference step of unknown x_j: the representable difference
+// (x_j + h) - x_j of the nominal step h = 2^-26 max(|x_j|, floor).
+__device__ __forceinline__ double step(double xj, double floor_) {
+  const double h = kRel * fmax(fabs(xj), floor_);
+  return (xj + h) - xj;
+}
+
+// Row j of every reactor's perturbed state: x_j + step(x_j).
+__global__ void __launch_bounds__(kThreads) k_perturb(const double *__restrict__ x, double *__restrict__ xp,
+                                                      int64_t B, int j, double floor_) {
+  const size_t row = (size_t)j * (size_t)B;
+  for (int64_t b = blockIdx.x * (int64_t)kThreads + threadIdx.x; b < B; b += (int64_t)gridDim.x * kThreads) {
+    const double xj = x[row + b];
+    xp[row + b] = xj + step(xj, floor_);
+  }
+}
+
+// Column j of every reactor's Jacobian, (F(x + h e_j) - F(x)) / h, then row j
+// of the perturbed state back to x_j.  Reads of F are coalesced over reactors.
+__global__ void __launch_bounds__(kThreads) k_column(const double *__restrict__ x, double *__restrict__ xp,
+                                                     const double *__restrict__ F0, const double *__restrict__ Fp,
+                                                     double *__restrict__ J, int64_t B, int n, int j, double floor_) {
+  const size_t row = (size_t)j * (size_t)B;
+  const size_t nn = (size_t)n * (size_t)n;
+  for (int64_t b = blockIdx.x * (int64_t)kThreads + threadIdx.x; b < B; b += (int64_t)gridDim.x * kThreads) {
+    const double xj = x[row + b];
+    const double h = step(xj, floor_);
+    double *Jb = J + (size_t)b * nn + j;
+    for (int r = 0; r < n; r++) {
+      const size_t i = (size_t)r * (size_t)B + b;
+      Jb[(size_t)r * n] = (Fp[i] - F0[i]) / h;
+    }
+    xp[row + b] = xj;
+  }
+}
+
+}  // namespace fd
+
+extern "C" psr_status psr_jacobian_fd(psr_mech_t m, const psr_conditions *c, const double *x, double *J,
+                                      double *work, void *stream) {
+  psr_status st = check_cond(m, c);
+  if (st != PSR_OK) return st;
+  if (!x || !J || !work) return fail(PSR_EINVAL, "null x, J or work");
+  const hipStream_t s = (hipStream_t)stream;
+  const int n = n_unknowns(m->dev, c->energy);
+  const int64_t B = c->n_reactors;
+  const size_t nB = (size_t)n * (size_t)B;
+  double *F0 = work, *Fp = work + nB, *xp = work + 2 * nB;
+  const int64_t blocks = (B + fd::kThreads - 1) / fd::kThreads;
+  const unsigned grid = (unsigned)std::min<int64_t>(blocks, 4096);
+  HIP_OK(hipMemcpyAsync(xp, x, nB * sizeof(double), hipMemcpyDeviceToDevice, s));
+  st = psr_residual(m, c, x, F0, nullptr, stream);
+  if (st != PSR_OK) return st;
+  for (int j = 0; j < n; j++) {
+    const double floor_ = j < m->N ? fd::kFloorY : 1.0;
+    hipLaunchKernelGGL(fd::k_perturb, dim3(grid), dim3(fd::kThreads), 0, s, x, xp, B, j, floor_);
+    HIP_OK(hipGetLastError());
+    st = psr_residual(m, c, xp, Fp, nullptr, stream);
+    if (st != PSR_OK) return st;
+    hipLaunchKernelGGL(fd::k_column, dim3(grid), dim3(fd::kThreads), 0, s, x, xp, F0, Fp, J, B, n, j, floor_);
+    HIP_OK(hipGetLastError());
+  }
+  return PSR_OK;
+}
+
 // Device scratch of the large-matrix LU entry point, grown on demand and kept
 // for the life of the process (one buffer per device, calls on a device are
 // serialised by the caller's stream use).
