@@ -93,12 +93,14 @@ def rate_kernel(P, B, steps=5, name="rate"):
             "frac_hbm": gbs / PEAK_HBM_GBS, "finite": ok}
 
 
-def newton_sweep(P, sizes, steps=3):
+def newton_sweep(P, sizes, steps=3, fd_max=100_000):
     """One Newton iteration per reactor (residual, analytic Jacobian, FP64 LU
     factorisation, triangular solves) on the 101/542 mechanism at the paper's
     single-iteration conditions (isothermal 1800 K, tau = 50 ms, inlet
     0.15/0.18/0.67 fuel/oxidizer/diluent, every reactor alike), at each batch
-    size; 'rate_jac' times the residual and Jacobian alone.  The oracle's
+    size; 'rate_jac' times the residual and Jacobian alone, 'rate_fd_jac' the
+    residual and the finite-difference Jacobian (n + 1 residual evaluations,
+    the paper's route; batches up to fd_max reactors).  The oracle's
     single-thread rate for the same iteration is measured on 20 reactors."""
     import ctypes as C
     import torch
@@ -143,8 +145,17 @@ def newton_sweep(P, sizes, steps=3):
             _lib.check(L.psr_lu_solve_batch(n, B, C.c_void_p(J.data_ptr()), C.c_void_p(piv.data_ptr()),
                                             C.c_void_p(rhs.data_ptr()), sp), "psr_lu_solve_batch")
 
+        fd_work = torch.empty((3 * n * B,), dtype=torch.float64, device=d) if B <= fd_max else None
+
+        def rate_fdjac():
+            P.residual(M, cd, energy, x, F, stream=stream)
+            P.jacobian_fd(M, cd, energy, x, J, work=fd_work, stream=stream)
+
+        legs = [("rate_jac", rate_jac), ("iteration", iteration)]
+        if fd_work is not None:
+            legs.append(("rate_fd_jac", rate_fdjac))
         row = {"reactors": B}
-        for name, fn in (("rate_jac", rate_jac), ("iteration", iteration)):
+        for name, fn in legs:
             fn()
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -160,7 +171,7 @@ def newton_sweep(P, sizes, steps=3):
         row["finite"] = bool(torch.isfinite(rhs).all().item())
         out["sizes"].append(row)
         print(f"newton101 B={B}: {row['iteration']['ms']:.3f} ms per iteration", file=sys.stderr, flush=True)
-        del cd, x, F, J, piv, info, rhs
+        del cd, x, F, J, piv, info, rhs, fd_work
         torch.cuda.empty_cache()
     try:
         from oracle import oracle as O
