@@ -186,3 +186,13 @@ def test_sweep_arguments_are_validated_on_the_host(lib):
         st = lib.psr_sweep_batch(grp, param, steps, C.cast(vals, C.c_void_p) if vals else None,
                                  C.byref(o), None, 0, None, None, None, None)
         assert st == _lib.PSR_EINVAL and words in lib.psr_last_error().decode(), words
+
+
+def test_fd_jacobian_rejects_null_arguments_on_the_host(lib):
+    """psr_jacobian_fd checks the mechanism and conditions before any
+    device work: a null mechanism or null conditions is PSR_EINVAL."""
+    from paper_2005_11468_amd import _lib
+    c = _lib.Conditions()
+    for cond in (None, C.byref(c)):
+        st = lib.psr_jacobian_fd(None, cond, None, None, None, None)
+        assert st == _lib.PSR_EINVAL and "null" in lib.psr_last_error().decode()
