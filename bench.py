@@ -31,7 +31,7 @@ PEAK_MFMA_F32_TFLOPS = 157.3
 # HBM bytes per launch of the mixed persistent solve kernel from rocprofv3
 # FETCH_SIZE / WRITE_SIZE passes scaled by a plain copy of known size
 # (profiles/solve_residual_53sp_pmc_traffic.md); None once that kernel changes.
-SOLVE_TRAFFIC_BYTES = 126.41e6
+SOLVE_TRAFFIC_BYTES = 126.6e6
 EXP_FLOPS = 20.0         # an FP64 exp counted as its ~20 vector instructions
 TOL = {0: 1e-8, 1: 1e-7}
 
