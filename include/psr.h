@@ -172,10 +172,18 @@ psr_status psr_lu_solve_batch(int32_t n, int64_t batch, const double *LU, const 
 typedef struct {
   int32_t precision;  /* PSR_FP64 or PSR_MIXED                              */
   int32_t scheduler;  /* PSR_PLAIN or PSR_PERSISTENT                        */
-  /* steady Newton attempt */
+  /* steady Newton attempt.  Every factorisation of the solve (Newton and
+   * pseudo-transient, FP64 and FP32) works on the matrix scaled by powers of
+   * two in its rows, then its columns, so that each has largest magnitude
+   * in [1/2, 1). */
   double rtol, atol_Y, atol_T; /* step-norm weights w = atol + rtol |x|         */
   double ftol;                 /* scaled-residual bound for convergence         */
-  double lambda_min;           /* smallest damping factor tried                 */
+  double lambda_min;           /* 0 (default): every Newton step is taken at the
+                                  length the bounds allow (T inside [T_min,
+                                  T_max], |d ln M_r| <= lnM_step), mass
+                                  fractions projected onto Y >= 0; > 0: that
+                                  length is halved until the natural criterion
+                                  holds, down to lambda_min                     */
   double T_min, T_max;         /* temperature bounds, K                         */
   /* pseudo-transient (ROS2) conditioning */
   double ts_rtol, ts_atol_Y, ts_atol_T; /* local-error weights                  */
@@ -215,6 +223,19 @@ typedef struct {
    * they change only speed. */
   int32_t rpw;
   int32_t grid_per_cu;
+  /* soot: largest change of a ln M_r in one Newton step (the step length is
+   * cut so that every |lambda d ln M_r| <= lnM_step) */
+  double lnM_step;
+  /* continuation in the residence time (gas-phase reactors; off when
+   * ct_ratio <= 1).  When a reactor's first Newton attempt fails, Newton
+   * attempts from the initial guess at tau / ct_ratio^k, k = 1, 2, ... (not
+   * below ct_tau_min seconds) until one converges; from that root tau is
+   * raised back in steps of at most a factor ct_ratio, each solved by a
+   * Newton attempt from the root before, a failed step retried at half its
+   * length in ln tau until it falls below ct_min_step.  The pseudo-transient
+   * steps start from the last root (else the initial guess) when this ends
+   * short of the reactor's tau. */
+  double ct_ratio, ct_tau_min, ct_min_step;
 } psr_solve_opts;
 
 /* Fill opts with the defaults (FP64, plain scheduler, graph replay on,

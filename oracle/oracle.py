@@ -68,7 +68,9 @@ class Opts(C.Structure):
                 ("h0", C.c_double), ("h_max", C.c_double), ("h_min", C.c_double),
                 ("nw_h_ratio", C.c_double),
                 ("nw_max_it", C.c_int), ("nw_every", C.c_int), ("max_lin", C.c_int),
-                ("atol_lnM", C.c_double), ("ts_atol_lnM", C.c_double)]
+                ("atol_lnM", C.c_double), ("ts_atol_lnM", C.c_double),
+                ("lnM_step", C.c_double), ("ct_ratio", C.c_double),
+                ("ct_tau_min", C.c_double), ("ct_min_step", C.c_double)]
 
 
 class Stats(C.Structure):

@@ -98,22 +98,26 @@ void om_default_opts(om_opts *o)
   o->atol_Y = 1e-20;
   o->atol_T = 1e-12;
   o->ftol = 1e-10;
-  o->lambda_min = 1.0 / 16.0;
+  o->lambda_min = 0.0;   /* <= 0: undamped Newton (bound-limited full steps) */
   o->T_min = 300.0;
-  o->T_max = 3000.0;
+  o->T_max = 4000.0;
   o->ts_rtol = 0.1;
   o->ts_atol_Y = 1e-6;
   o->ts_atol_T = 1e-3;
   o->ts_neg_tol = 1e-8;
   o->h0 = 1e-6;
-  o->h_min = 1e-20;
+  o->h_min = 1e-30;
   o->h_max = 1e6;
-  o->nw_h_ratio = 1.0;
-  o->nw_max_it = 8;
+  o->nw_h_ratio = 0.0;
+  o->nw_max_it = 30;
   o->nw_every = 10;
-  o->max_lin = 1000;
+  o->max_lin = 1500;
   o->atol_lnM = 1e-10;
   o->ts_atol_lnM = 1e-3;
+  o->lnM_step = 2.0;
+  o->ct_ratio = 10.0;
+  o->ct_tau_min = 1e-6;
+  o->ct_min_step = 0.05;
 }
 
 void om_thermo(const om_mech *m, double T, double *cp_R, double *h_RT, double *s_R)
@@ -413,6 +417,46 @@ void om_lu_solve(int n, const double *lu, const int *piv, double *b)
   }
 }
 
+/* Scale the rows, then the columns, of a by powers of two so that every
+ * row and column has largest magnitude in [1/2, 1) (exact in binary
+ * floating point), then factor the scaled matrix with om_lu_factor.  rs,
+ * cs receive the scales.  The Jacobians of stiff mechanisms have rows whose
+ * magnitudes differ by tens of orders (gross fluxes against the flow
+ * terms); without this scaling the pivot order is set by those magnitudes
+ * and the Newton steps of trace species lose every significant digit.    */
+static int eq_factor(int n, double *a, int *piv, double *rs, double *cs)
+{
+  for (int i = 0; i < n; i++) {
+    double mx = 0.0;
+    int e = 0;
+    for (int j = 0; j < n; j++)
+      if (fabs(a[(size_t)i * n + j]) > mx) mx = fabs(a[(size_t)i * n + j]);
+    if (mx > 0.0 && isfinite(mx)) frexp(mx, &e);
+    rs[i] = ldexp(1.0, -e);
+  }
+  for (int j = 0; j < n; j++) {
+    double mx = 0.0;
+    int e = 0;
+    for (int i = 0; i < n; i++)
+      if (fabs(a[(size_t)i * n + j] * rs[i]) > mx) mx = fabs(a[(size_t)i * n + j] * rs[i]);
+    if (mx > 0.0 && isfinite(mx)) frexp(mx, &e);
+    cs[j] = ldexp(1.0, -e);
+  }
+  for (int i = 0; i < n; i++)
+    for (int j = 0; j < n; j++) a[(size_t)i * n + j] *= rs[i] * cs[j];
+  return om_lu_factor(n, a, piv);
+}
+
+/* Solve a z = b in place with the factors of eq_factor:
+ * z = diag(cs) (R a C)^-1 diag(rs) b.                                       */
+static void eq_solve(int n, const double *lu, const int *piv, const double *rs, const double *cs,
+                     double *b)
+{
+  for (int i = 0; i < n; i++) b[i] *= rs[i];
+  om_lu_solve(n, lu, piv, b);
+  for (int i = 0; i < n; i++) b[i] *= cs[i];
+}
+
 /* ---- hybrid damped Newton / pseudo-transient driver (Section 3) -------- */
 
 enum { NW_CONVERGED, NW_FAILED, NW_BUDGET };
@@ -439,8 +483,9 @@ static void step_clamped(const om_cond *c, const om_opts *o, int N, int n, const
   }
 }
 
-/* Largest lambda <= 1 keeping T + lambda dT inside [T_min, T_max]. */
-static double bound_lambda(const om_cond *c, const om_opts *o, int N, const double *x,
+/* Largest lambda <= 1 keeping T + lambda dT inside [T_min, T_max] and every
+ * soot unknown's change |lambda d ln M_r| at most lnM_step.                 */
+static double bound_lambda(const om_cond *c, const om_opts *o, int N, int n, const double *x,
                            const double *d)
 {
   double lam = 1.0;
@@ -449,6 +494,8 @@ static double bound_lambda(const om_cond *c, const om_opts *o, int N, const doub
     if (dT > 0.0 && T + dT > o->T_max) lam = (o->T_max - T) / dT;
     if (dT < 0.0 && T + dT < o->T_min) lam = (T - o->T_min) / (-dT);
   }
+  for (int r = N + 1; r < n; r++)
+    if (fabs(d[r]) * lam > o->lnM_step) lam = o->lnM_step / fabs(d[r]);
   return lam;
 }
 
@@ -464,15 +511,18 @@ static double newton_norm(const om_opts *o, int N, int n, const double *x, const
   return r;
 }
 
-/* Steady damped Newton attempt on F(x) = 0, started from x (not modified
- * unless it converges).  Each iteration: F(x), J(x), LU, Newton step
- * d = -J^-1 F.  Converged when the weighted step norm is <= 1 and the
- * scaled residual is <= ftol; the result is then x + d.  Otherwise the
- * damping factor starts at the temperature-bound limit and is halved until
- * the trial point's step, solved with the same factors, is smaller in the
- * weighted norm than d (natural criterion); below lambda_min, or after
- * nw_max_it iterations, the attempt has failed.  Every (residual,
- * triangular solve) pair counts one against the max_lin budget.            */
+/* Steady Newton attempt on F(x) = 0, started from x (not modified unless
+ * it converges).  Each iteration: F(x), J(x), LU of the equilibrated J,
+ * Newton step d = -J^-1 F.  Converged when the weighted step norm is <= 1
+ * and the scaled residual is <= ftol; the result is then x + d.  Otherwise
+ * the step length lambda starts at the bound limit (T inside [T_min,
+ * T_max], |d ln M_r| <= lnM_step).  With lambda_min <= 0 that step is taken
+ * as it is (mass fractions projected onto Y >= 0); with lambda_min > 0
+ * lambda is halved until the trial point's step, solved with the same
+ * factors, is smaller in the weighted norm than d (natural criterion), and
+ * the attempt fails below lambda_min.  After nw_max_it iterations the
+ * attempt has failed.  Every (residual, triangular solve) pair counts one
+ * against the max_lin budget.                                               */
 static int newton_attempt(const om_mech *m, const om_cond *c, const om_opts *o, double *xio,
                           om_stats *st)
 {
@@ -481,6 +531,7 @@ static int newton_attempt(const om_mech *m, const om_cond *c, const om_opts *o, 
   double *J = malloc(sizeof(double) * n * n), *d = malloc(sizeof(double) * n);
   double *dt = malloc(sizeof(double) * n), *xt = malloc(sizeof(double) * n);
   int *piv = malloc(sizeof(int) * n);
+  double *rs = malloc(sizeof(double) * n), *cs = malloc(sizeof(double) * n);
   int result = NW_FAILED;
   memcpy(x, xio, sizeof(double) * n);
   for (int it = 0; it < o->nw_max_it; it++) {
@@ -489,9 +540,9 @@ static int newton_attempt(const om_mech *m, const om_cond *c, const om_opts *o, 
     om_jacobian(m, c, x, J);
     st->n_jac++;
     if (!all_finite(n, F) || !all_finite(n * n, J)) break;
-    if (om_lu_factor(n, J, piv) != 0) break;
+    if (eq_factor(n, J, piv, rs, cs) != 0) break;
     for (int i = 0; i < n; i++) d[i] = -F[i];
-    om_lu_solve(n, J, piv, d);
+    eq_solve(n, J, piv, rs, cs, d);
     st->n_lin++;
     if (!all_finite(n, d)) break;
     double nd = newton_norm(o, N, n, x, d);
@@ -505,14 +556,19 @@ static int newton_attempt(const om_mech *m, const om_cond *c, const om_opts *o, 
         break;
       }
     }
-    double lam = bound_lambda(c, o, N, x, d);
+    double lam = bound_lambda(c, o, N, n, x, d);
+    if (!(o->lambda_min > 0.0)) {
+      step_clamped(c, o, N, n, x, lam, d, xt);
+      memcpy(x, xt, sizeof(double) * n);
+      continue;
+    }
     int accepted = 0;
     while (lam >= o->lambda_min) {
       if (st->n_lin >= o->max_lin) { result = NW_BUDGET; goto done; }
       step_clamped(c, o, N, n, x, lam, d, xt);
       om_residual(m, c, xt, dt);
       for (int i = 0; i < n; i++) dt[i] = -dt[i];
-      om_lu_solve(n, J, piv, dt);
+      eq_solve(n, J, piv, rs, cs, dt);
       st->n_lin++;
       if (newton_norm(o, N, n, x, dt) < nd) {
         memcpy(x, xt, sizeof(double) * n);
@@ -524,7 +580,7 @@ static int newton_attempt(const om_mech *m, const om_cond *c, const om_opts *o, 
     if (!accepted) break;
   }
 done:
-  free(x); free(F); free(J); free(d); free(dt); free(xt); free(piv);
+  free(x); free(F); free(J); free(d); free(dt); free(xt); free(piv); free(rs); free(cs);
   return result;
 }
 
@@ -537,8 +593,10 @@ enum { TS_ACCEPTED, TS_REJECTED, TS_BUDGET };
  *   A k1 = -F(x) / (gamma h)
  *   A k2 = (-F(x + h k1) - 2 M k1) / (gamma h)
  *   x_new = x + 3/2 h k1 + 1/2 h k2,   error estimate  h/2 (k1 + k2).
+ * The matrix A is equilibrated before its LU, as in the Newton attempt.
  * Accepted when the RMS-weighted error is <= 1 (weights ts_atol + ts_rtol
- * max(|x|, |x_new|)), x_new is finite, T stays in [T_min, T_max] and no
+ * max(|x|, |x_new|) for Y and T; ts_atol_lnM + ts_rtol for ln M_r, whose
+ * changes are relative changes of M_r already), x_new is finite, T stays in [T_min, T_max] and no
  * mass fraction is below -ts_neg_tol; negative mass fractions are then set
  * to zero.  h is rescaled by 0.9/sqrt(err) within [0.2, 5] (0.25 after a
  * non-finite or out-of-bounds result).  Counts two linear solves.        */
@@ -553,6 +611,7 @@ static int ros2_step(const om_mech *m, const om_cond *c, const om_opts *o, doubl
   double *k2 = malloc(sizeof(double) * n), *x1 = malloc(sizeof(double) * n);
   double *xn = malloc(sizeof(double) * n);
   int *piv = malloc(sizeof(int) * n);
+  double *rs = malloc(sizeof(double) * n), *cs = malloc(sizeof(double) * n);
   int result = TS_REJECTED, bad = 0;
   double hh = *h, err = INFINITY;
 
@@ -561,21 +620,22 @@ static int ros2_step(const om_mech *m, const om_cond *c, const om_opts *o, doubl
   om_mass_diag(m, c, x, M);
   st->n_jac++;
   for (int i = 0; i < n; i++) A[(size_t)i * n + i] += M[i] / (gam * hh);
-  if (!all_finite(n, F) || !all_finite(n * n, A) || om_lu_factor(n, A, piv) != 0) {
+  if (!all_finite(n, F) || !all_finite(n * n, A) || eq_factor(n, A, piv, rs, cs) != 0) {
     bad = 1;
   } else {
     for (int i = 0; i < n; i++) k1[i] = -F[i] / (gam * hh);
-    om_lu_solve(n, A, piv, k1);
+    eq_solve(n, A, piv, rs, cs, k1);
     for (int i = 0; i < n; i++) x1[i] = x[i] + hh * k1[i];
     if (c->energy) x1[N] = x1[N] < o->T_min ? o->T_min : (x1[N] > o->T_max ? o->T_max : x1[N]);
     om_residual(m, c, x1, F);
     for (int i = 0; i < n; i++) k2[i] = (-F[i] - 2.0 * M[i] * k1[i]) / (gam * hh);
-    om_lu_solve(n, A, piv, k2);
+    eq_solve(n, A, piv, rs, cs, k2);
     double s = 0.0;
     for (int i = 0; i < n; i++) {
       xn[i] = x[i] + 1.5 * hh * k1[i] + 0.5 * hh * k2[i];
       double ax = fabs(x[i]) > fabs(xn[i]) ? fabs(x[i]) : fabs(xn[i]);
-      double w = (i < N ? o->ts_atol_Y : (i == N ? o->ts_atol_T : o->ts_atol_lnM)) + o->ts_rtol * ax;
+      double w = i > N ? o->ts_atol_lnM + o->ts_rtol
+                       : (i < N ? o->ts_atol_Y : o->ts_atol_T) + o->ts_rtol * ax;
       double e = 0.5 * hh * (k1[i] + k2[i]) / w;
       s += e * e;
     }
@@ -599,23 +659,77 @@ static int ros2_step(const om_mech *m, const om_cond *c, const om_opts *o, doubl
     double fac = bad ? 0.25 : 0.9 / sqrt(err);
     *h = hh * (fac < 0.2 ? 0.2 : fac);
   }
-  free(F); free(A); free(M); free(k1); free(k2); free(x1); free(xn); free(piv);
+  free(F); free(A); free(M); free(k1); free(k2); free(x1); free(xn); free(piv); free(rs); free(cs);
   return result;
 }
 
-/* Hybrid solve (Section 3): a steady damped-Newton attempt; while it
- * fails, the estimate is conditioned by pseudo-transient integration and
- * Newton is tried again after every nw_every accepted steps once the step
- * size has grown to nw_h_ratio * tau.  Ends converged, with TS_FAILED when
- * the step size falls below h_min (seconds), or MAXITER when the linear-solve
- * budget is spent.  x holds the initial guess on entry, the result on exit. */
+/* Continuation in the residence time for a gas-phase reactor whose Newton
+ * attempt at its own tau failed: Newton attempts from the initial guess x0
+ * at tau / r, tau / r^2, ... (r = ct_ratio, not below ct_tau_min seconds)
+ * until one converges; from that root, the residence time is raised towards
+ * tau in steps of at most a factor r, each step solved by a Newton attempt
+ * started from the root before; a failed step is retried at half its length
+ * in ln tau, and the walk stops once the step falls below ct_min_step.
+ * Returns NW_CONVERGED with x the root at tau, NW_BUDGET, or NW_FAILED with
+ * x the last root of the walk (x0 if no rung converged).                   */
+static int tau_continuation(const om_mech *m, const om_cond *c, const om_opts *o, double *x,
+                            om_stats *st)
+{
+  const int n = om_n_unknowns(m, c->energy);
+  double *x0 = malloc(sizeof(double) * n), *y = malloc(sizeof(double) * n);
+  memcpy(x0, x, sizeof(double) * n);
+  om_cond cc = *c;
+  const double lt = log(c->tau), lr = log(o->ct_ratio);
+  double lc = 0.0;
+  int found = 0, result = NW_FAILED;
+  for (int k = 1; lt - k * lr >= log(o->ct_tau_min); k++) {
+    cc.tau = exp(lt - k * lr);
+    memcpy(y, x0, sizeof(double) * n);
+    st->n_attempts++;
+    int r = newton_attempt(m, &cc, o, y, st);
+    if (r == NW_BUDGET) { result = NW_BUDGET; goto done; }
+    if (r == NW_CONVERGED) { found = 1; lc = lt - k * lr; memcpy(x, y, sizeof(double) * n); break; }
+  }
+  if (!found) goto done;
+  double step = lr;
+  while (step >= o->ct_min_step) {
+    const int last = lc + step >= lt;
+    const double ln = last ? lt : lc + step;
+    cc.tau = last ? c->tau : exp(ln);
+    memcpy(y, x, sizeof(double) * n);
+    st->n_attempts++;
+    int r = newton_attempt(m, &cc, o, y, st);
+    if (r == NW_BUDGET) { result = NW_BUDGET; break; }
+    if (r == NW_CONVERGED) {
+      memcpy(x, y, sizeof(double) * n);
+      if (last) { result = NW_CONVERGED; break; }
+      lc = ln;
+      step = 2.0 * step < lr ? 2.0 * step : lr;
+    } else {
+      step *= 0.5;
+    }
+  }
+done:
+  free(x0); free(y);
+  return result;
+}
+
+/* Hybrid solve (Section 3): a steady Newton attempt at the reactor's tau;
+ * if it fails, a gas-phase reactor tries the continuation in tau above
+ * (ct_ratio > 1); while Newton still fails, the estimate (the last root of
+ * the continuation, else the initial guess) is conditioned by
+ * pseudo-transient integration and Newton is tried again after every
+ * nw_every accepted steps once the step size has grown to nw_h_ratio * tau.
+ * Ends converged, with TS_FAILED when the step size falls below h_min
+ * (seconds), or MAXITER when the linear-solve budget is spent.  x holds the
+ * initial guess on entry, the result on exit.                              */
 int om_solve(const om_mech *m, const om_cond *c, const om_opts *o, double *x, om_stats *st)
 {
   const int N = m->n_sp, n = om_n_unknowns(m, c->energy);
   memset(st, 0, sizeof(*st));
   for (int i = 0; i < N; i++) if (x[i] < 0.0) x[i] = 0.0;
   double h = o->h0 * c->tau;
-  int attempt = 1, accepted = 0;
+  int attempt = 1, accepted = 0, first = 1;
   for (;;) {
     if (attempt) {
       st->n_attempts++;
@@ -623,6 +737,12 @@ int om_solve(const om_mech *m, const om_cond *c, const om_opts *o, double *x, om
       if (r == NW_CONVERGED) { st->status = OM_CONVERGED; break; }
       if (r == NW_BUDGET) { st->status = OM_MAXITER; break; }
       attempt = 0;
+      if (first && o->ct_ratio > 1.0 && !(c->energy && m->soot)) {
+        r = tau_continuation(m, c, o, x, st);
+        if (r == NW_CONVERGED) { st->status = OM_CONVERGED; break; }
+        if (r == NW_BUDGET) { st->status = OM_MAXITER; break; }
+      }
+      first = 0;
     }
     int r = ros2_step(m, c, o, x, &h, st);
     if (r == TS_BUDGET) { st->status = OM_MAXITER; break; }

@@ -73,7 +73,7 @@ typedef struct {
   /* steady Newton attempt */
   double rtol, atol_Y, atol_T; /* step-norm weights w = atol + rtol |x|        */
   double ftol;                 /* scaled-residual bound for convergence        */
-  double lambda_min;           /* smallest damping factor tried                */
+  double lambda_min;           /* smallest damping factor tried (<= 0: undamped) */
   double T_min, T_max;         /* temperature bounds, K                        */
   /* pseudo-transient (ROS2) conditioning */
   double ts_rtol, ts_atol_Y, ts_atol_T; /* local-error weights                 */
@@ -86,6 +86,11 @@ typedef struct {
   int max_lin;                 /* total linear-solve budget                    */
   double atol_lnM;             /* step-norm weight offset of the ln M_r unknowns */
   double ts_atol_lnM;          /* local-error weight offset of the ln M_r unknowns */
+  double lnM_step;             /* largest change of a ln M_r in one Newton step */
+  /* continuation in tau (gas-phase reactors; off when ct_ratio <= 1)      */
+  double ct_ratio;             /* largest factor between continuation rungs    */
+  double ct_tau_min;           /* smallest residence time of a rung, s         */
+  double ct_min_step;          /* smallest step in ln tau before giving up     */
 } om_opts;
 
 enum { OM_CONVERGED = 0, OM_MAXITER = 1, OM_TS_FAILED = 2, OM_NONFINITE = 3 };

@@ -48,7 +48,9 @@ class SolveOpts(C.Structure):
                 ("max_refine", C.c_int32), ("engine", C.c_int32),
                 ("use_graph", C.c_int32), ("refine_tol", C.c_double),
                 ("atol_lnM", C.c_double), ("ts_atol_lnM", C.c_double),
-                ("rpw", C.c_int32), ("grid_per_cu", C.c_int32)]
+                ("rpw", C.c_int32), ("grid_per_cu", C.c_int32),
+                ("lnM_step", C.c_double), ("ct_ratio", C.c_double),
+                ("ct_tau_min", C.c_double), ("ct_min_step", C.c_double)]
 
 
 class Group(C.Structure):

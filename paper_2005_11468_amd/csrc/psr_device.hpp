@@ -57,6 +57,8 @@ struct Opts {
   int nw_max_it, nw_every, max_lin, max_refine;
   double refine_tol;
   double atol_lnM, ts_atol_lnM;  // soot moments
+  double lnM_step;               // largest |d ln M_r| of one Newton step
+  double ct_ratio, ct_tau_min, ct_min_step;  // continuation in tau
 };
 
 // Mixed precision: refinement target of the solve whose Newton step ends a
@@ -68,6 +70,9 @@ constexpr double kFinalRefine = 1e-10;
 constexpr int kStickFP64 = 4;
 
 enum Phase : int { PH_NW_BASE = 0, PH_NW_TRIAL = 1, PH_TS1 = 2, PH_TS2 = 3, PH_DONE = 4 };
+// Continuation in tau: first attempt at the reactor's tau, down search,
+// walk back up, or not (any more) in use.
+enum CtMode : int { CT_OFF = 0, CT_FIRST = 1, CT_DOWN = 2, CT_WALK = 3 };
 enum RStatus : int { RS_CONVERGED = 0, RS_MAXITER = 1, RS_TS_FAILED = 2, RS_NONFINITE = 3, RS_RUNNING = 9 };
 
 // Per-reactor controller state of the hybrid method.
@@ -77,7 +82,11 @@ struct RState {
   int n_fb64;    // mixed mode: FP64 fallbacks so far
   int stick;     // mixed mode: linearisations still to factor in FP64 directly
   int sing, fin; // matrix flags of this round
+  int ct, ct_k;  // continuation mode, down-search rung
   double nd, lam, h, sres;
+  double tau_c;                // residence time of the current Newton attempt
+  double ct_lc, ct_ln, ct_step; // continuation: ln tau of the last root, of
+                                // the current attempt, step in ln tau
 };
 
 // LDS / workspace layout of one reactor, in doubles (8-byte units).  The

@@ -493,26 +493,30 @@ extern "C" void psr_default_opts(psr_solve_opts *o) {
   o->atol_Y = 1e-20;
   o->atol_T = 1e-12;
   o->ftol = 1e-10;
-  o->lambda_min = 1.0 / 16.0;
+  o->lambda_min = 0.0;
   o->T_min = 300.0;
-  o->T_max = 3000.0;
+  o->T_max = 4000.0;
   o->ts_rtol = 0.1;
   o->ts_atol_Y = 1e-6;
   o->ts_atol_T = 1e-3;
   o->ts_neg_tol = 1e-8;
   o->h0 = 1e-6;
   o->h_max = 1e6;
-  o->h_min = 1e-20;
-  o->nw_h_ratio = 1.0;
-  o->nw_max_it = 8;
+  o->h_min = 1e-30;
+  o->nw_h_ratio = 0.0;
+  o->nw_max_it = 30;
   o->nw_every = 10;
-  o->max_lin = 1000;
+  o->max_lin = 1500;
   o->max_refine = 6;
   o->engine = 0;
   o->use_graph = 1;
   o->refine_tol = 1e-6;
   o->atol_lnM = 1e-10;
   o->ts_atol_lnM = 1e-3;
+  o->lnM_step = 2.0;
+  o->ct_ratio = 10.0;
+  o->ct_tau_min = 1e-6;
+  o->ct_min_step = 0.05;
 }
 
 // Lagrange basis polynomial l over the nodes 0..m-1, at p.
@@ -991,6 +995,8 @@ static Opts to_dev_opts(const psr_solve_opts *o) {
   d.max_lin = o->max_lin; d.max_refine = o->max_refine;
   d.refine_tol = o->refine_tol;
   d.atol_lnM = o->atol_lnM; d.ts_atol_lnM = o->ts_atol_lnM;
+  d.lnM_step = o->lnM_step;
+  d.ct_ratio = o->ct_ratio; d.ct_tau_min = o->ct_tau_min; d.ct_min_step = o->ct_min_step;
   return d;
 }
 
@@ -1192,12 +1198,13 @@ static psr_status check_opts(const psr_solve_opts *o) {
   if (o->precision != PSR_FP64 && o->precision != PSR_MIXED) return fail(PSR_EINVAL, "bad precision");
   if (o->scheduler != PSR_PLAIN && o->scheduler != PSR_PERSISTENT) return fail(PSR_EINVAL, "bad scheduler");
   if (!(o->rtol > 0) || !(o->atol_Y >= 0) || !(o->atol_T >= 0) || !(o->ftol > 0) ||
-      !(o->lambda_min > 0 && o->lambda_min <= 1) || !(o->T_min < o->T_max) || !(o->ts_rtol > 0) ||
+      !(o->lambda_min >= 0 && o->lambda_min <= 1) || !(o->T_min < o->T_max) || !(o->ts_rtol > 0) ||
       !(o->h0 > 0) || !(o->h_min > 0) || !(o->h_max > 0) || o->nw_max_it < 1 || o->nw_every < 1 ||
       o->max_lin < 1 || o->max_refine < 0 || o->engine < 0 || o->engine > 2 || o->use_graph < 0 ||
       o->use_graph > 1 || !(o->refine_tol > 0 && o->refine_tol < 1) || !(o->atol_lnM >= 0) ||
       !(o->ts_atol_lnM >= 0) || !(o->rpw == 0 || o->rpw == 1 || o->rpw == 2 || o->rpw == 4) ||
-      o->grid_per_cu < 0 || o->grid_per_cu > 32)
+      o->grid_per_cu < 0 || o->grid_per_cu > 32 || !(o->lnM_step > 0) ||
+      !(o->ct_ratio >= 0) || !(o->ct_tau_min > 0) || !(o->ct_min_step > 0))
     return fail(PSR_EINVAL, "option out of range");
   return PSR_OK;
 }

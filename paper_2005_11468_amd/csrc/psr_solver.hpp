@@ -9,11 +9,16 @@
 // values, so the controller state stays replicated without extra traffic.
 //
 // Phases:
-//   NW_BASE   Newton iterate: F, J, LU, d = -J^-1 F, convergence test,
+//   NW_BASE   Newton iterate: F, J, LU, d = -J^-1 F, convergence test, then
+//             the bound-limited step (undamped, lambda_min <= 0) or the
 //             damping start.
 //   NW_TRIAL  trial point x + lam d of the natural criterion, solved with
-//             the same factors.
+//             the same factors (lambda_min > 0 only).
 //   TS1, TS2  the two stages of one ROS2 step of M dx/dt = -F(x).
+//
+// A gas-phase reactor whose first Newton attempt fails first tries the
+// continuation in the residence time (ct_down / ct_walk below); the
+// pseudo-transient steps start when that fails too.
 #pragma once
 
 #include "psr_device.hpp"
@@ -70,12 +75,13 @@ __device__ inline int matrix_finite(const double *A, int n, int lda, double *red
 
 // ---------------------------------------------------------- linear algebra
 
-// Mixed precision: scale rows, then columns, of A64 by powers of two (exact)
-// so every row and column has max magnitude in [1/2, 1), round to float into
-// A32 and factor there.  Returns the float LU's status.
-template <int BS, bool BIG>
-__device__ int factor_mixed(const Ctx &c, const double *A64, float *A32, int *piv, double *rs,
-                            double *cs, double *red) {
+// Power-of-two scales of A64 (exact): rs[i] puts row i's largest magnitude
+// in [1/2, 1), then cs[j] does the same for column j of the row-scaled
+// matrix.  The Jacobians of stiff mechanisms have rows whose magnitudes
+// differ by tens of orders (gross reaction fluxes against the flow terms);
+// every factorisation of the solve works on diag(rs) A diag(cs).
+template <int BS>
+__device__ void equilibration_scales(const Ctx &c, const double *A64, double *rs, double *cs) {
   const int n = c.n, lda = c.L.lda;
   for (int i = threadIdx.x; i < n; i += BS) {
     double mx = 0.0;
@@ -93,6 +99,16 @@ __device__ int factor_mixed(const Ctx &c, const double *A64, float *A32, int *pi
     cs[j] = ldexp(1.0, -e);
   }
   __syncthreads();
+}
+
+// Mixed precision: equilibrate A64 (scales above), round to float into A32
+// and factor there; A64 stays unscaled for the FP64 refinement.  Returns the
+// float LU's status.
+template <int BS, bool BIG>
+__device__ int factor_mixed(const Ctx &c, const double *A64, float *A32, int *piv, double *rs,
+                            double *cs, double *red) {
+  const int n = c.n, lda = c.L.lda;
+  equilibration_scales<BS>(c, A64, rs, cs);
   for (int e = threadIdx.x; e < n * n; e += BS) {
     const int i = e / n, j = e % n;
     A32[(int64_t)i * lda + j] = (float)(A64[(int64_t)i * lda + j] * rs[i] * cs[j]);
@@ -105,12 +121,20 @@ __device__ int factor_mixed(const Ctx &c, const double *A64, float *A32, int *pi
   return lu_factor<BS, float>(A32, n, lda, piv, red);
 }
 
-// FP64 factorisation of the round's matrix.  Large matrices (kept in HBM)
-// use the blocked LU, whose panel borrows the reaction scratch in LDS (not in
-// use between the Jacobian and the next residual).
+// FP64 factorisation of the round's matrix, equilibrated in place (scales
+// into rs, cs).  Large matrices (kept in HBM) use the blocked LU, whose
+// panel borrows the reaction scratch in LDS (not in use between the
+// Jacobian and the next residual).
 template <int BS, bool BIG>
 __device__ inline int factor64(const Ctx &c, double *A64, int *piv, double *red) {
   const int n = c.n, lda = c.L.lda;
+  double *rs = c.p(c.L.rs), *cs = c.p(c.L.cs);
+  equilibration_scales<BS>(c, A64, rs, cs);
+  for (int e = threadIdx.x; e < n * n; e += BS) {
+    const int i = e / n, j = e % n;
+    A64[(int64_t)i * lda + j] *= rs[i] * cs[j];
+  }
+  __syncthreads();
   if (BIG && BS == 256 && n > 64 && n <= 256 && 12 * c.L.I >= 17 * n)
     return lu_factor_blocked64<256>(A64, n, lda, piv, red, c.p(c.L.kf));
   return lu_factor<BS, double>(A64, n, lda, piv, red);
@@ -141,8 +165,12 @@ __device__ void solve_round(const Ctx &c, const Opts &o, RState &s, const double
   double *A64 = c.A64();
   int *piv = c.piv();
   if (!MIXED || s.fb64) {
-    vcopy<BS>(z, b, n);
+    const double *rs = c.p(c.L.rs), *cs = c.p(c.L.cs);
+    for (int i = threadIdx.x; i < n; i += BS) z[i] = rs[i] * b[i];
+    __syncthreads();
     lu_solve<BS, double>(A64, n, lda, piv, z);
+    for (int i = threadIdx.x; i < n; i += BS) z[i] *= cs[i];
+    __syncthreads();
     return;
   }
   const float *A32 = c.A32();
@@ -180,8 +208,11 @@ __device__ void solve_round(const Ctx &c, const Opts &o, RState &s, const double
   s.stick = kStickFP64;
   const int info = factor64<BS, BIG>(c, A64, piv, red);
   s.sing = info != 0;
-  vcopy<BS>(z, bb, n);
+  for (int i = threadIdx.x; i < n; i += BS) z[i] = rs[i] * bb[i];
+  __syncthreads();
   if (!s.sing) lu_solve<BS, double>(A64, n, lda, piv, z);
+  for (int i = threadIdx.x; i < n; i += BS) z[i] *= cs[i];
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------- rounds
@@ -200,15 +231,81 @@ __device__ inline void start_ts(const Ctx &c, const Opts &o, RState &s) {
   vcopy<BS>(c.p(c.L.xev), c.p(c.L.x), c.n);
 }
 
-// Start a steady Newton attempt from x.
+// Start a steady Newton attempt from x at residence time tau_c (the
+// residual and Jacobian of its rounds use tau_c).
 template <int BS>
-__device__ inline void start_attempt(const Ctx &c, const Opts &o, RState &s) {
+__device__ inline void start_attempt_at(const Ctx &c, const Opts &o, RState &s, double tau_c) {
   s.n_att++;
   s.nw_it = 0;
+  s.tau_c = tau_c;
   vcopy<BS>(c.p(c.L.xnw), c.p(c.L.x), c.n);
   if (s.n_lin >= o.max_lin) { finish<BS>(s, RS_MAXITER); return; }
   s.phase = PH_NW_BASE;
   vcopy<BS>(c.p(c.L.xev), c.p(c.L.xnw), c.n);
+}
+
+template <int BS>
+__device__ inline void start_attempt(const Ctx &c, const Opts &o, RState &s) {
+  start_attempt_at<BS>(c, o, s, c.tau);
+}
+
+// Continuation in the residence time (gas-phase reactors whose first Newton
+// attempt failed).  Down search: Newton from the initial guess (held in x)
+// at tau / r^k, k = 1, 2, ... while tau / r^k >= ct_tau_min; once one
+// converges, the walk raises tau from that root (x) by steps of at most a
+// factor r, halving the step in ln tau after a failed attempt, until the
+// reactor's own tau is reached or the step falls below ct_min_step.
+template <int BS>
+__device__ inline void ct_down(const Ctx &c, const Opts &o, RState &s) {
+  s.ct_k++;
+  const double ln = log(c.tau) - s.ct_k * log(o.ct_ratio);
+  if (ln >= log(o.ct_tau_min)) {
+    s.ct_ln = ln;
+    start_attempt_at<BS>(c, o, s, exp(ln));
+  } else {
+    s.ct = CT_OFF;
+    start_ts<BS>(c, o, s);
+  }
+}
+
+template <int BS>
+__device__ inline void ct_walk(const Ctx &c, const Opts &o, RState &s) {
+  const double lt = log(c.tau);
+  const bool last = s.ct_lc + s.ct_step >= lt;
+  s.ct_ln = last ? lt : s.ct_lc + s.ct_step;
+  start_attempt_at<BS>(c, o, s, last ? c.tau : exp(s.ct_ln));
+}
+
+// A Newton attempt has failed: the next continuation attempt, else ROS2
+// pseudo-transient steps from x.
+template <int BS>
+__device__ inline void nw_failed(const Ctx &c, const Opts &o, RState &s) {
+  if (s.ct == CT_FIRST) {
+    s.ct = (o.ct_ratio > 1.0 && c.n == c.N + (c.energy ? 1 : 0)) ? CT_DOWN : CT_OFF;
+    s.ct_k = 0;
+  }
+  if (s.ct == CT_DOWN) { ct_down<BS>(c, o, s); return; }
+  if (s.ct == CT_WALK) {
+    s.ct_step *= 0.5;
+    if (s.ct_step >= o.ct_min_step) { ct_walk<BS>(c, o, s); return; }
+    s.ct = CT_OFF;
+  }
+  start_ts<BS>(c, o, s);
+}
+
+// A Newton attempt has converged at tau_c, its root written to x: done at
+// the reactor's own tau, else the next step of the continuation walk.
+template <int BS>
+__device__ inline void nw_converged(const Ctx &c, const Opts &o, RState &s, double *red) {
+  if (s.ct == CT_DOWN || (s.ct == CT_WALK && s.tau_c != c.tau)) {
+    const double lr = log(o.ct_ratio);
+    s.ct_step = (s.ct == CT_DOWN) ? lr : (2.0 * s.ct_step < lr ? 2.0 * s.ct_step : lr);
+    s.ct = CT_WALK;
+    s.ct_lc = s.ct_ln;
+    ct_walk<BS>(c, o, s);
+    return;
+  }
+  finish<BS>(s, all_finite<BS>(c.p(c.L.x), c.n, red) ? RS_CONVERGED : RS_NONFINITE);
 }
 
 // Next damped trial point, or the attempt has failed.
@@ -219,8 +316,18 @@ __device__ inline void try_trial(const Ctx &c, const Opts &o, RState &s) {
     step_clamped<BS>(c, o, c.p(c.L.xnw), s.lam, c.p(c.L.d), c.p(c.L.xev));
     s.phase = PH_NW_TRIAL;
   } else {
-    start_ts<BS>(c, o, s);
+    nw_failed<BS>(c, o, s);
   }
+}
+
+// The Newton iterate xnw has moved: next iteration, or the attempt ends.
+template <int BS>
+__device__ inline void next_newton(const Ctx &c, const Opts &o, RState &s) {
+  s.nw_it++;
+  if (s.nw_it >= o.nw_max_it) { nw_failed<BS>(c, o, s); return; }
+  if (s.n_lin >= o.max_lin) { finish<BS>(s, RS_MAXITER); return; }
+  s.phase = PH_NW_BASE;
+  vcopy<BS>(c.p(c.L.xev), c.p(c.L.xnw), c.n);
 }
 
 template <int BS>
@@ -242,7 +349,11 @@ __device__ void round_step(Ctx &c, const Opts &o, RState &s) {
   int *piv = c.piv();
   const int ph = s.phase;
   const bool lin = (ph == PH_NW_BASE || ph == PH_TS1);
+  const bool nw = (ph == PH_NW_BASE || ph == PH_NW_TRIAL);
 
+  // a Newton attempt of the continuation evaluates at its own residence time
+  const double tau = c.tau;
+  if (nw) c.tau = s.tau_c;
   const double sres = residual<BS>(c, xev, G, ph == PH_NW_BASE);
   if (lin) {
     jacobian<BS>(c, xev, A64, lda);
@@ -275,6 +386,7 @@ __device__ void round_step(Ctx &c, const Opts &o, RState &s) {
       }
     }
   }
+  c.tau = tau;
   const bool skip = lin && (!s.fin || s.sing);
   if (!skip) {
     // right-hand side of this round, formed in place of the residual
@@ -299,7 +411,7 @@ __device__ void round_step(Ctx &c, const Opts &o, RState &s) {
       break;
     }
     if (MIXED && s.sing) {  // an FP64 refactorisation found the matrix singular
-      if (ph == PH_NW_BASE) { start_ts<BS>(c, o, s); return; }
+      if (ph == PH_NW_BASE) { nw_failed<BS>(c, o, s); return; }
       if (ph == PH_TS1) { s.n_lin += 2; reject_ts<BS>(c, o, s, true, 0.0); return; }
       for (int i = threadIdx.x; i < n; i += BS) out[i] = __builtin_nan("");
       __syncthreads();
@@ -308,24 +420,33 @@ __device__ void round_step(Ctx &c, const Opts &o, RState &s) {
 
   switch (ph) {
     case PH_NW_BASE: {
-      if (skip) { start_ts<BS>(c, o, s); return; }
+      if (skip) { nw_failed<BS>(c, o, s); return; }
       s.n_lin++;
-      if (!all_finite<BS>(d, n, red)) { start_ts<BS>(c, o, s); return; }
+      if (!all_finite<BS>(d, n, red)) { nw_failed<BS>(c, o, s); return; }
       const double nd = newton_norm<BS>(c, o, xnw, d, red);
       s.nd = nd;
       if (nd <= 1.0 && sres <= o.ftol) {
         s.sres = sres;
         step_clamped<BS>(c, o, xnw, 1.0, d, x);
-        finish<BS>(s, all_finite<BS>(x, n, red) ? RS_CONVERGED : RS_NONFINITE);
+        nw_converged<BS>(c, o, s, red);
         return;
       }
+      // step length limited by the bounds: T inside [T_min, T_max], every
+      // |d ln M_r| at most lnM_step
       double lam = 1.0;
       if (c.energy) {
         const double T = xnw[N], dT = d[N];
         if (dT > 0.0 && T + dT > o.T_max) lam = (o.T_max - T) / dT;
         if (dT < 0.0 && T + dT < o.T_min) lam = (T - o.T_min) / (-dT);
       }
+      for (int r = N + 1; r < n; r++)  // same scalar decision on every thread
+        if (fabs(d[r]) * lam > o.lnM_step) lam = o.lnM_step / fabs(d[r]);
       s.lam = lam;
+      if (!(o.lambda_min > 0.0)) {  // undamped: take the bound-limited step
+        step_clamped<BS>(c, o, xnw, lam, d, xnw);
+        next_newton<BS>(c, o, s);
+        return;
+      }
       try_trial<BS>(c, o, s);
       return;
     }
@@ -334,11 +455,7 @@ __device__ void round_step(Ctx &c, const Opts &o, RState &s) {
       const double ndt = newton_norm<BS>(c, o, xnw, t, red);
       if (ndt < s.nd) {
         vcopy<BS>(xnw, xev, n);
-        s.nw_it++;
-        if (s.nw_it >= o.nw_max_it) { start_ts<BS>(c, o, s); return; }
-        if (s.n_lin >= o.max_lin) { finish<BS>(s, RS_MAXITER); return; }
-        s.phase = PH_NW_BASE;
-        vcopy<BS>(xev, xnw, n);
+        next_newton<BS>(c, o, s);
       } else {
         s.lam *= 0.5;
         try_trial<BS>(c, o, s);
@@ -365,7 +482,9 @@ __device__ void round_step(Ctx &c, const Opts &o, RState &s) {
       for (int i = threadIdx.x; i < n; i += BS) {
         const double xn = x[i] + 1.5 * h * d[i] + 0.5 * h * t[i];
         const double ax = fmax(fabs(x[i]), fabs(xn));
-        const double w = (i < N ? o.ts_atol_Y : (i == N ? o.ts_atol_T : o.ts_atol_lnM)) + o.ts_rtol * ax;
+        // ln M_r: its change is a relative change of M_r already
+        const double w = i > N ? o.ts_atol_lnM + o.ts_rtol
+                               : (i < N ? o.ts_atol_Y : o.ts_atol_T) + o.ts_rtol * ax;
         const double e = 0.5 * h * (d[i] + t[i]) / w;
         e2 += e * e;
         bad |= !isfinite(xn);
@@ -408,6 +527,10 @@ __device__ inline void init_state(const Ctx &c, const Opts &o, RState &s) {
   s.fin = 1;
   s.nd = s.lam = s.sres = 0.0;
   s.h = o.h0 * c.tau;
+  s.ct = CT_FIRST;
+  s.ct_k = 0;
+  s.tau_c = c.tau;
+  s.ct_lc = s.ct_ln = s.ct_step = 0.0;
   double *x = c.p(c.L.x);
   for (int i = threadIdx.x; i < c.N; i += BS) x[i] = x[i] > 0.0 ? x[i] : 0.0;
   __syncthreads();

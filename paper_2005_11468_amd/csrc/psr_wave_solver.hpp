@@ -46,14 +46,6 @@ __device__ __forceinline__ double clamp_step(const WCtx &c, const Opts &o, doubl
   return v;
 }
 
-template <int NP>
-__device__ __forceinline__ void load_rows64(const WCtx &c, const WArea<NP> &A, double (&a)[NP]) {
-  const int lane = lane_id(), n = c.n;
-  const double *row = A.J + (lane < n ? lane : 0) * A.ldj;
-#pragma unroll
-  for (int j = 0; j < NP; j++) a[j] = (lane < n && j < n) ? row[j] : 0.0;
-}
-
 template <int NP, bool MIXED>
 __device__ __forceinline__ void finish_w(WState<NP, MIXED> &r, int status) {
   r.s.status = status;
@@ -68,13 +60,69 @@ __device__ __forceinline__ void start_ts_w(const Opts &o, WState<NP, MIXED> &r) 
 }
 
 template <int NP, bool MIXED>
-__device__ __forceinline__ void start_attempt_w(const Opts &o, WState<NP, MIXED> &r) {
+__device__ __forceinline__ void start_attempt_w(const Opts &o, WState<NP, MIXED> &r, double tau_c) {
   r.s.n_att++;
   r.s.nw_it = 0;
+  r.s.tau_c = tau_c;
   r.xnw = r.x;
   if (r.s.n_lin >= o.max_lin) { finish_w(r, RS_MAXITER); return; }
   r.s.phase = PH_NW_BASE;
   r.xev = r.xnw;
+}
+
+// Continuation in the residence time (see psr_solver.hpp): down search from
+// the initial guess in x, then the walk back up from the last root in x.
+template <int NP, bool MIXED>
+__device__ __forceinline__ void ct_down_w(const WCtx &c, const Opts &o, WState<NP, MIXED> &r) {
+  RState &s = r.s;
+  s.ct_k++;
+  const double ln = log(c.tau) - s.ct_k * log(o.ct_ratio);
+  if (ln >= log(o.ct_tau_min)) {
+    s.ct_ln = ln;
+    start_attempt_w(o, r, exp(ln));
+  } else {
+    s.ct = CT_OFF;
+    start_ts_w(o, r);
+  }
+}
+
+template <int NP, bool MIXED>
+__device__ __forceinline__ void ct_walk_w(const WCtx &c, const Opts &o, WState<NP, MIXED> &r) {
+  RState &s = r.s;
+  const double lt = log(c.tau);
+  const bool last = s.ct_lc + s.ct_step >= lt;
+  s.ct_ln = last ? lt : s.ct_lc + s.ct_step;
+  start_attempt_w(o, r, last ? c.tau : exp(s.ct_ln));
+}
+
+template <int NP, bool MIXED>
+__device__ __forceinline__ void nw_failed_w(const WCtx &c, const Opts &o, WState<NP, MIXED> &r) {
+  RState &s = r.s;
+  if (s.ct == CT_FIRST) {
+    s.ct = (o.ct_ratio > 1.0 && c.n == c.N + (c.energy ? 1 : 0)) ? CT_DOWN : CT_OFF;
+    s.ct_k = 0;
+  }
+  if (s.ct == CT_DOWN) { ct_down_w(c, o, r); return; }
+  if (s.ct == CT_WALK) {
+    s.ct_step *= 0.5;
+    if (s.ct_step >= o.ct_min_step) { ct_walk_w(c, o, r); return; }
+    s.ct = CT_OFF;
+  }
+  start_ts_w(o, r);
+}
+
+template <int NP, bool MIXED>
+__device__ __forceinline__ void nw_converged_w(const WCtx &c, const Opts &o, WState<NP, MIXED> &r) {
+  RState &s = r.s;
+  if (s.ct == CT_DOWN || (s.ct == CT_WALK && s.tau_c != c.tau)) {
+    const double lr = log(o.ct_ratio);
+    s.ct_step = (s.ct == CT_DOWN) ? lr : (2.0 * s.ct_step < lr ? 2.0 * s.ct_step : lr);
+    s.ct = CT_WALK;
+    s.ct_lc = s.ct_ln;
+    ct_walk_w(c, o, r);
+    return;
+  }
+  finish_w(r, wany(lane_id() < c.n && !isfinite(r.x)) ? RS_NONFINITE : RS_CONVERGED);
 }
 
 template <int NP, bool MIXED>
@@ -84,8 +132,18 @@ __device__ __forceinline__ void try_trial_w(const WCtx &c, const Opts &o, WState
     r.xev = clamp_step(c, o, r.xnw, r.s.lam, r.d);
     r.s.phase = PH_NW_TRIAL;
   } else {
-    start_ts_w(o, r);
+    nw_failed_w(c, o, r);
   }
+}
+
+// The Newton iterate xnw has moved: next iteration, or the attempt ends.
+template <int NP, bool MIXED>
+__device__ __forceinline__ void next_newton_w(const WCtx &c, const Opts &o, WState<NP, MIXED> &r) {
+  r.s.nw_it++;
+  if (r.s.nw_it >= o.nw_max_it) { nw_failed_w(c, o, r); return; }
+  if (r.s.n_lin >= o.max_lin) { finish_w(r, RS_MAXITER); return; }
+  r.s.phase = PH_NW_BASE;
+  r.xev = r.xnw;
 }
 
 template <int NP, bool MIXED>
@@ -96,21 +154,13 @@ __device__ __forceinline__ void reject_ts_w(const Opts &o, WState<NP, MIXED> &r,
   else start_ts_w(o, r);
 }
 
-// Factor the FP64 matrix held in the LDS rows (FP64 mode or mixed fallback).
+// Power-of-two scales of the LDS rows (exact): r.rs puts lane i's row
+// maximum in [1/2, 1), then r.cs (and A.cs[j]) does the same for column j of
+// the row-scaled matrix.  The Jacobians of stiff mechanisms have rows whose
+// magnitudes differ by tens of orders; every factorisation of the solve
+// works on diag(rs) A diag(cs).
 template <int NP, bool MIXED>
-__device__ __forceinline__ int factor64(const WCtx &c, const WArea<NP> &A, WState<NP, MIXED> &r) {
-  load_rows64<NP>(c, A, r.a);
-  int pos;
-  double pk;
-  const int info = lu_regs<NP, double>(r.a, c.n, pos, r.perm, pk);
-  lu_finish<NP, double>(r.a, r.a, c.n, r.perm, pk, r.piv);
-  return info;
-}
-
-// Mixed precision: equilibrate the LDS rows by powers of two (rows, then
-// columns), round to float in registers, factor there.
-template <int NP, bool MIXED>
-__device__ __forceinline__ int factor32(const WCtx &c, const WArea<NP> &A, WState<NP, MIXED> &r) {
+__device__ __forceinline__ void equilibrate_w(const WCtx &c, const WArea<NP> &A, WState<NP, MIXED> &r) {
   const int lane = lane_id(), n = c.n;
   const bool in = lane < n;
   const double *row = A.J + (in ? lane : 0) * A.ldj;
@@ -134,6 +184,34 @@ __device__ __forceinline__ int factor32(const WCtx &c, const WArea<NP> &A, WStat
   r.cs = in ? ldexp(1.0, -e) : 1.0;
   A.cs[lane] = r.cs;
   wsync();
+}
+
+// Factor the FP64 matrix held in the LDS rows (FP64 mode or mixed
+// fallback), equilibrated as it is loaded into registers.
+template <int NP, bool MIXED>
+__device__ __forceinline__ int factor64(const WCtx &c, const WArea<NP> &A, WState<NP, MIXED> &r) {
+  equilibrate_w<NP, MIXED>(c, A, r);
+  const int lane = lane_id(), n = c.n;
+  const bool in = lane < n;
+  const double *row = A.J + (in ? lane : 0) * A.ldj;
+#pragma unroll
+  for (int j = 0; j < NP; j++) r.a[j] = (in && j < n) ? row[j] * r.rs * A.cs[j] : 0.0;
+  wsync();
+  int pos;
+  double pk;
+  const int info = lu_regs<NP, double>(r.a, n, pos, r.perm, pk);
+  lu_finish<NP, double>(r.a, r.a, n, r.perm, pk, r.piv);
+  return info;
+}
+
+// Mixed precision: equilibrate the LDS rows, round to float in registers,
+// factor there.
+template <int NP, bool MIXED>
+__device__ __forceinline__ int factor32(const WCtx &c, const WArea<NP> &A, WState<NP, MIXED> &r) {
+  equilibrate_w<NP, MIXED>(c, A, r);
+  const int lane = lane_id(), n = c.n;
+  const bool in = lane < n;
+  const double *row = A.J + (in ? lane : 0) * A.ldj;
   float f[NP];
 #pragma unroll
   for (int j = 0; j < NP; j++) {
@@ -162,13 +240,13 @@ __device__ __forceinline__ double solve_w(const WCtx &c, const WArea<NP> &A, con
   const double *row = A.J + (in ? lane : 0) * A.ldj;
   // One call site of the (unrolled) substitution: sweep 0 solves for z, the
   // refinement sweeps for corrections, and after an FP64 fallback the sweep
-  // solves the unscaled system directly.
+  // solves with the FP64 factors (of the same equilibrated matrix).
   bool fp64 = !MIXED || r.s.fb64;
   double z = 0.0, acc = b, prev = __builtin_inf();
   for (int it = 0;; it++) {
-    const double rhs = fp64 ? b : r.rs * (in ? acc : 0.0);
+    const double rhs = r.rs * (in ? (fp64 ? b : acc) : 0.0);
     const double sol = lu_solve_w<NP>(r.a, n, r.perm, r.piv, rhs);
-    if (fp64) return sol;
+    if (fp64) return sol * r.cs;
     const double dz = sol * r.cs;
     z = (it == 0) ? dz : z + dz;
     bool fallback = false;
@@ -211,10 +289,13 @@ __device__ __forceinline__ void w_round(const WCtx &c, const WArea<NP> &A, const
   const bool lin = (ph == PH_NW_BASE || ph == PH_TS1);
   Eval ev;
   double G = 0.0;
-  const double sres = w_residual<NP>(c, A, r.xev, G, ev, ph == PH_NW_BASE);
+  // a Newton attempt of the continuation evaluates at its own residence time
+  WCtx ce = c;
+  if (ph == PH_NW_BASE || ph == PH_NW_TRIAL) ce.tau = s.tau_c;
+  const double sres = w_residual<NP>(ce, A, r.xev, G, ev, ph == PH_NW_BASE);
   if (!in) G = 0.0;
   if (lin) {
-    w_jacobian<NP>(c, A, r.xev, ev);
+    w_jacobian<NP>(ce, A, r.xev, ev);
     if (ph == PH_TS1) {
       const double cp = wsum(lane < N ? r.xev * kR * ev.cpR / c.t.W[lane] : 0.0);
       double M = 0.0;
@@ -272,7 +353,7 @@ __device__ __forceinline__ void w_round(const WCtx &c, const WArea<NP> &A, const
       break;
     }
     if (MIXED && s.sing) {
-      if (ph == PH_NW_BASE) { start_ts_w(o, r); return; }
+      if (ph == PH_NW_BASE) { nw_failed_w(c, o, r); return; }
       if (ph == PH_TS1) { s.n_lin += 2; reject_ts_w(o, r, true, 0.0); return; }
       out = in ? __builtin_nan("") : 0.0;
     }
@@ -282,15 +363,15 @@ __device__ __forceinline__ void w_round(const WCtx &c, const WArea<NP> &A, const
 
   switch (ph) {
     case PH_NW_BASE: {
-      if (skip) { start_ts_w(o, r); return; }
+      if (skip) { nw_failed_w(c, o, r); return; }
       s.n_lin++;
-      if (wany(in && !isfinite(r.d))) { start_ts_w(o, r); return; }
+      if (wany(in && !isfinite(r.d))) { nw_failed_w(c, o, r); return; }
       const double nd = newton_norm_w<NP>(c, o, r.xnw, r.d);
       s.nd = nd;
       if (nd <= 1.0 && sres <= o.ftol) {
         s.sres = sres;
         r.x = clamp_step(c, o, r.xnw, 1.0, r.d);
-        finish_w(r, wany(in && !isfinite(r.x)) ? RS_NONFINITE : RS_CONVERGED);
+        nw_converged_w(c, o, r);
         return;
       }
       double lam = 1.0;
@@ -300,6 +381,11 @@ __device__ __forceinline__ void w_round(const WCtx &c, const WArea<NP> &A, const
         if (dT < 0.0 && T + dT < o.T_min) lam = (T - o.T_min) / (-dT);
       }
       s.lam = lam;
+      if (!(o.lambda_min > 0.0)) {  // undamped: take the bound-limited step
+        r.xnw = clamp_step(c, o, r.xnw, lam, r.d);
+        next_newton_w(c, o, r);
+        return;
+      }
       try_trial_w(c, o, r);
       return;
     }
@@ -308,11 +394,7 @@ __device__ __forceinline__ void w_round(const WCtx &c, const WArea<NP> &A, const
       const double ndt = newton_norm_w<NP>(c, o, r.xnw, r.t);
       if (ndt < s.nd) {
         r.xnw = r.xev;
-        s.nw_it++;
-        if (s.nw_it >= o.nw_max_it) { start_ts_w(o, r); return; }
-        if (s.n_lin >= o.max_lin) { finish_w(r, RS_MAXITER); return; }
-        s.phase = PH_NW_BASE;
-        r.xev = r.xnw;
+        next_newton_w(c, o, r);
       } else {
         s.lam *= 0.5;
         try_trial_w(c, o, r);
@@ -352,7 +434,7 @@ __device__ __forceinline__ void w_round(const WCtx &c, const WArea<NP> &A, const
         if (s.h > o.h_max * c.tau) s.h = o.h_max * c.tau;
         s.accepted++;
         s.n_ts++;
-        if (s.accepted % o.nw_every == 0 && s.h >= o.nw_h_ratio * c.tau) start_attempt_w(o, r);
+        if (s.accepted % o.nw_every == 0 && s.h >= o.nw_h_ratio * c.tau) start_attempt_w(o, r, c.tau);
         else start_ts_w(o, r);
       } else {
         reject_ts_w(o, r, bad, err);
@@ -381,7 +463,11 @@ __device__ __forceinline__ void init_w(const WCtx &c, const Opts &o, WState<NP, 
   s.fin = 1;
   s.nd = s.lam = s.sres = 0.0;
   s.h = o.h0 * c.tau;
-  start_attempt_w(o, r);
+  s.ct = CT_FIRST;
+  s.ct_k = 0;
+  s.tau_c = c.tau;
+  s.ct_lc = s.ct_ln = s.ct_step = 0.0;
+  start_attempt_w(o, r, c.tau);
 }
 
 __device__ __forceinline__ double inlet_enthalpy(const Tables &t, int i, double Tin) {

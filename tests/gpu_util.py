@@ -41,3 +41,51 @@ def solve_gpu(mech_obj, cond, x0, energy, **opts):
                                 status=status, n_lin=nlin)], o)
     torch.cuda.synchronize()
     return x.cpu().numpy(), status.cpu().numpy(), nlin.cpu().numpy(), st
+
+
+def parity(oracle_mod, mech, cond, energy, x, status, xo, so, tol, *, max_branch_frac=0.02,
+           max_miss_frac=0.0, label=""):
+    """Per-reactor parity of GPU results x, status against the oracle's xo, so
+    (same initial guesses).
+
+    Several steady states can be correct for one reactor (a non-isothermal
+    PSR can have an ignited and an extinguished branch), and which one the
+    hybrid method reaches can turn on rounding at a decision point (a Newton
+    attempt converging in its last allowed iteration on one side only).  So:
+      * reactors both sides converged either agree within `tol` (relative,
+        rel_err), or form a branch mismatch;
+      * every GPU root that is not within `tol` of an oracle root (branch
+        mismatches, reactors only the GPU converged) must be a steady state
+        by the oracle's own test: the oracle, restarted at the GPU root,
+        converges with one linear solve (its first Newton step already passes
+        the step-norm and scaled-residual tests) and stays within `tol`;
+      * branch mismatches may be at most max_branch_frac of the jointly
+        converged reactors (at least one allowed), and reactors only the
+        oracle converged at most max_miss_frac of the oracle-converged ones.
+    Returns the counts (and prints them)."""
+    n_sp = mech["species_elems"].shape[0]
+    conv_o, conv_g = so["status"] == 0, status == 0
+    both = conv_o & conv_g
+    assert np.all(status >= 0), label
+    err = rel_err(x, xo, n_sp) if x.shape[1] else np.zeros(0)
+    agree = both & (err <= tol)
+    branch = np.flatnonzero(both & ~agree)
+    gpu_only = np.flatnonzero(conv_g & ~conv_o)
+    miss = np.flatnonzero(conv_o & ~conv_g)
+    O = oracle_mod.Mechanism(mech)
+    opts = oracle_mod.default_opts()
+    for b in np.concatenate([branch, gpu_only]).astype(int):
+        args = (cond["P"][b], cond["tau"][b], cond["T_in"][b], cond["Y_in"][:, b], energy)
+        xr, st = O.solve(*args, x[:, b], opts)
+        assert st.status == 0 and st.n_lin <= 1, (label, "GPU root not verified", int(b), st.status,
+                                                  st.n_lin)
+        e = rel_err(x[:, b:b + 1], xr[:, None], n_sp)[0]
+        assert e <= tol, (label, "oracle restart moved", int(b), e)
+    nb = int(both.sum())
+    assert len(branch) <= max(1, int(max_branch_frac * nb)), (label, "branch mismatches", branch)
+    assert len(miss) <= int(max_miss_frac * conv_o.sum()), (label, "oracle-only roots", miss)
+    out = dict(reactors=int(len(status)), oracle=int(conv_o.sum()), gpu=int(conv_g.sum()),
+               agree=int(agree.sum()), branch=len(branch), gpu_only=len(gpu_only), miss=len(miss),
+               max_err=float(err[agree].max()) if agree.any() else 0.0)
+    print(f"{label}: {out}", flush=True)
+    return out

@@ -2,18 +2,19 @@
 100/600 and 200/1200 species/reactions, energy equation) solved in one
 psr_solve_batch call.  The 31-unknown group runs on the wavefront engine,
 the 101- and 201-unknown groups on the workgroup engine with their matrices
-in HBM (they do not fit one workgroup's LDS).  Seeded prefixes of each group;
-the oracle runs on the same reactors."""
+in HBM (they do not fit one workgroup's LDS).  Seeded samples of each group
+over the whole residence-time range, at the default linear-solve budget; the
+oracle runs on the same reactors."""
 import numpy as np
 import pytest
 
-from tests.gpu_util import cond_dev, dev, rel_err
+from tests.gpu_util import cond_dev, dev, parity
 
 pytestmark = pytest.mark.gpu
 
 TOL = {0: 1e-8, 1: 1e-7}  # PSR_FP64, PSR_MIXED
-SAMPLE = {"uneven_a": 24, "uneven_b": 10, "uneven_c": 8}
-MAX_LIN = 4000  # the larger mechanisms need more linear solves than the default 1000
+# seeded samples of each group over its whole residence-time range (1e-6 to 1 s)
+SAMPLE = {"uneven_a": 48, "uneven_b": 40, "uneven_c": 16}
 
 
 @pytest.fixture(scope="module")
@@ -29,16 +30,13 @@ def groups(oracle_mod):
     from psr_inputs import uneven_workload
     out = []
     for name, mech, cond, x0 in uneven_workload(1.0):
-        # the first reactors with tau <= 1e-2 s: at longer residence times most
-        # reactors of the larger mechanisms use up the linear-solve budget (in
-        # the oracle too), which leaves nothing to compare
-        idx = np.flatnonzero(cond["tau"] <= 1e-2)[:SAMPLE[name]]
+        rng = np.random.default_rng(7)
+        idx = np.sort(rng.choice(x0.shape[1], SAMPLE[name], replace=False))
         cond = {k: np.ascontiguousarray(v[..., idx]) for k, v in cond.items()}
         x0 = np.ascontiguousarray(x0[:, idx])
         B = len(idx)
-        print(f"oracle: {name} B={B}", flush=True)
-        xo, so = oracle_mod.solve_batch(mech, cond, x0, True, processes=8,
-                                        opts=oracle_mod.default_opts(max_lin=MAX_LIN))
+        print(f"oracle: {name} B={B} tau {cond['tau'].min():.1e}..{cond['tau'].max():.1e}", flush=True)
+        xo, so = oracle_mod.solve_batch(mech, cond, x0, True, processes=8)
         out.append((name, mech, cond, x0, xo, so))
     return out
 
@@ -54,36 +52,27 @@ def _solve_all(P, groups, **opts):
         nlin = torch.zeros((B,), dtype=torch.int32, device="cuda:0")
         gl.append(dict(mech=M, cond=cond_dev(cond), energy=True, x=x, status=status, n_lin=nlin))
         keep.append(M)
-    st, _ = P.solve_batch(gl, P.default_opts(max_lin=MAX_LIN, **opts))
+    st, _ = P.solve_batch(gl, P.default_opts(**opts))
     torch.cuda.synchronize()
     return [(g["x"].cpu().numpy(), g["status"].cpu().numpy(), g["n_lin"].cpu().numpy()) for g in gl], st
 
 
 def _check_group(oracle_mod, name, mech, cond, xo, so, x, status, tol):
-    """Jointly converged reactors must agree with the oracle within tol.  Which
-    reactors converge within the linear-solve budget is not unique: the
-    error-controlled pseudo-time stepping takes different step sequences under
-    different rounding, and a few reactors end on either side of the budget.
-    So a reactor converged here but not by the oracle must be a steady state by
-    the oracle's own scaled residual, and most oracle-converged reactors must
-    converge here too."""
-    conv_o = so["status"] == 0
-    conv_g = status == 0
-    both = conv_o & conv_g
-    print(f"{name}: oracle converged {conv_o.sum()}/{len(conv_o)}, GPU {conv_g.sum()}, both {both.sum()}",
-          flush=True)
-    assert np.all(status >= 0)
-    assert both.sum() >= conv_o.sum() - max(1, conv_o.sum() // 4)
-    if both.any():
-        err = rel_err(x[:, both], xo[:, both], mech["species_elems"].shape[0])
-        assert err.max() <= tol, (name, np.sort(err)[-3:])
-    extra = np.flatnonzero(conv_g & ~conv_o)
-    if extra.size:
-        OM = oracle_mod.Mechanism(mech)
-        for b in extra:
-            r = OM.scaled_residual(cond["P"][b], cond["tau"][b], cond["T_in"][b], cond["Y_in"][:, b], True,
-                                   x[:, b])
-            assert r <= 1e-9, (name, int(b), r)
+    """Oracle parity of one group (see tests.gpu_util.parity): the oracle
+    converges at least 85 % of the sample at the default budget (on samples
+    of 256 and more: 95.5 to 99.4 % per mechanism), GPU roots
+    that differ from the oracle's are verified as steady states by the
+    oracle, and the GPU converges as many reactors as the oracle, up to one
+    in twenty.  On these mechanisms a reactor's path (a Newton attempt of the
+    continuation that converges in its last allowed iteration on one side
+    only, then different pseudo-time steps) can turn on rounding, so a few
+    reactors end inside the budget on one side only, in both directions
+    (measured: 38 of 40 converged on each side, one reactor each way); at
+    most one in sixteen oracle roots may be missed."""
+    assert (so["status"] == 0).mean() >= 0.85, (name, so["status"])
+    out = parity(oracle_mod, mech, cond, True, x, status, xo, so, tol, label=name,
+                 max_miss_frac=1.0 / 16)
+    assert out["gpu"] >= out["oracle"] - max(1, out["oracle"] // 20), (name, out)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
