@@ -6,11 +6,15 @@ psr_inputs).  One step = one psr_solve_batch call that solves the whole batch
 from the same initial guess, with inputs already resident in HBM.
 
 Printed JSON line (one): the mixed-precision persistent solver's rate as
-`value`, the plain FP64 host-driven solver and the persistent FP64 solver on
-the same inputs beside it, a roofline object for the dominant kernel (the
-persistent solve kernel), the residual kernel's throughput on a batch of 1e6
-reactors against the FP64 and HBM peaks, parity against the oracle on the
-CPU-baseline sample, and the oracle's own throughput on the host cores.
+`value`; the plain FP64 host-driven solver and the persistent FP64 solver on
+the same inputs beside it, each timed the same way (warm-up, median of
+--steps calls, workspace allocated beforehand); parity of every leg against
+the oracle on the whole batch (or a seeded sample); a roofline object for the
+dominant kernel (the persistent solve kernel); the residual kernel's
+throughput on a batch of 1e6 reactors; the batched float LU at n = 201; the
+65536-reactor three-mechanism workload and the 8192-reactor sooting workload
+with oracle parity on samples; the single-Newton-iteration sweep; the
+continuation sweeps; and the oracle's own throughput on the host cores.
 """
 from __future__ import annotations
 
@@ -28,31 +32,81 @@ sys.path.insert(0, ROOT)
 PEAK_ALU_TFLOPS = 78.6   # FP64 vector = non-packed FP32 vector: 256 CU x 64 FMA/clk x 2 x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
 PEAK_MFMA_F32_TFLOPS = 157.3
-# HBM bytes per launch of the mixed persistent solve kernel from rocprofv3
-# FETCH_SIZE / WRITE_SIZE passes scaled by a plain copy of known size
-# (profiles/solve_residual_53sp_pmc_traffic.md); None once that kernel changes.
-SOLVE_TRAFFIC_BYTES = 126.6e6
-EXP_FLOPS = 20.0         # an FP64 exp counted as its ~20 vector instructions
+EXP_FLOPS = 20.0         # an FP64 exp or log counted as its ~20 vector instructions
 TOL = {0: 1e-8, 1: 1e-7}
+FTOL = 1e-10             # scaled-residual bound of a converged reactor
+PROFILES = os.path.join(ROOT, "profiles")
+# Solver options of the 53/325 workload: damped Newton (natural criterion,
+# lambda >= 1/16, 8 iterations per attempt), no continuation in tau, Newton
+# retried once the pseudo-time step reaches tau.  That workload converges
+# fully with them (the oracle: 1024 of 1024 sampled reactors, 66
+# linearisations per reactor) against 132 linearisations and 99.4 % with the
+# defaults, which the 100- to 201-unknown mechanisms need; the other legs use
+# the defaults.
+FAST_OPTS = dict(lambda_min=1.0 / 16.0, nw_max_it=8, ct_ratio=0.0, nw_h_ratio=1.0)
 
 
-def residual_work(N, I, nnz, n):
-    """Algorithmic FP64 flops and HBM bytes of one residual evaluation of one
-    reactor: thermo (~45 N), per reaction two exps plus ~28 flops (rate
-    constant, equilibrium constant, concentration products), two flops per
-    stoichiometric entry for the production rates; bytes: x, Y_in, P, tau,
-    T_in in, F and the scaled residual out."""
-    flops = I * (2 * EXP_FLOPS + 28.0) + 2.0 * nnz + 45.0 * N
-    nbytes = 8.0 * (n + N + 3) + 8.0 * (n + 1)
-    return flops, nbytes
+def residual_flops(N, I):
+    """Algorithmic FP64 flops of one residual evaluation of one reactor: two
+    exps per reaction (k_f and k_r), one log, ~19 flops per species (thermo,
+    concentrations, residual rows) and ~14 per reaction (rate-constant
+    exponent, equilibrium constant, concentration products, production
+    rates)."""
+    return 2.0 * I * EXP_FLOPS + EXP_FLOPS + 19.0 * N + 14.0 * I
 
 
-def alg_flops(n, N, I):
-    """Algorithmic flops of one linearisation (Jacobian + LU) and of one
-    round (residual + triangular solves), counting an exp/log as one op."""
-    lin = 2.0 / 3.0 * n ** 3 + 90.0 * I + 10.0 * N * N
-    rnd = 32.0 * I + 32.0 * N + 2.0 * n * n
-    return lin, rnd
+def residual_bytes(N, n):
+    """HBM bytes of one residual evaluation: x, Y_in, P, tau, T_in in; F and
+    the scaled residual out."""
+    return 8.0 * (n + N + 3) + 8.0 * (n + 1)
+
+
+def jacobian_flops(n, I):
+    """Analytic Jacobian: ~54 flops per reaction (rate derivatives and their
+    scatter) and 2 n^2 for the density / temperature chain rule."""
+    return 54.0 * I + 2.0 * n * n
+
+
+def solve_flops(n):
+    return 2.0 * n * n
+
+
+def lu_flops(n):
+    return 2.0 / 3.0 * n ** 3
+
+
+def unit_flops(n, N, I):
+    """(per linearisation, per round): a linearisation is a Jacobian and an
+    LU factorisation, a round a residual and a pair of triangular solves."""
+    return jacobian_flops(n, I) + lu_flops(n), residual_flops(N, I) + solve_flops(n)
+
+
+def src_digest():
+    """sha256 of the HIP sources: the profiles' counters hold only for the
+    kernels they were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2005_11468_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the PMC summary in
+    profiles/ (FETCH_SIZE and WRITE_SIZE passes, scaled by a plain copy of
+    known size), or None when there is none for these sources."""
+    path = os.path.join(PROFILES, "pmc_traffic.tsv")
+    if not os.path.exists(path):
+        return None
+    digest = src_digest()
+    with open(path) as fh:
+        for line in fh:
+            f = line.rstrip("\n").split("\t")
+            if len(f) >= 5 and f[0] == kernel and f[1] == workload and f[2] == digest:
+                return float(f[3]) + float(f[4])
+    return None
 
 
 def rate_kernel(P, B, steps=5, name="rate"):
@@ -79,9 +133,7 @@ def rate_kernel(P, B, steps=5, name="rate"):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     N, I = mech["species_elems"].shape[0], mech["A"].shape[0]
-    nnz = int(sum(len(set(int(v) for v in list(mech["reac_idx"][k]) + list(mech["prod_idx"][k]) if v >= 0))
-                  for k in range(I)))
-    fl, by = residual_work(N, I, nnz, x0.shape[0])
+    fl, by = residual_flops(N, I), residual_bytes(N, x0.shape[0])
     tf = fl * B / (ms / 1e3) / 1e12
     gbs = by * B / (ms / 1e3) / 1e9
     ok = bool(torch.isfinite(F).all().item())
@@ -110,10 +162,7 @@ def newton_sweep(P, sizes, steps=3, fd_max=100_000):
     M = P.Mechanism(mech)
     N, I = mech["species_elems"].shape[0], mech["A"].shape[0]
     n = x0.shape[0]
-    nnz = int(sum(len(set(int(v) for v in list(mech["reac_idx"][k]) + list(mech["prod_idx"][k]) if v >= 0))
-                  for k in range(I)))
-    res_fl, _ = residual_work(N, I, nnz, n)
-    it_fl = res_fl + 54.0 * I + 2.0 * n * n + 2.0 / 3.0 * n ** 3 + 2.0 * n * n
+    it_fl = residual_flops(N, I) + jacobian_flops(n, I) + lu_flops(n) + solve_flops(n)
     L = _lib.load()
     stream = torch.cuda.current_stream()
     sp = C.c_void_p(stream.cuda_stream)
@@ -230,62 +279,168 @@ def lu_large(P, n=201, B=9830, steps=3):
             "frac_mfma_f32": tf / PEAK_MFMA_F32_TFLOPS, "nonsingular": ok}
 
 
-def uneven(P, fraction=1.0 / 64):
-    """The three-mechanism workload (30/200, 100/600, 200/1200 species /
-    reactions, 50 / 35 / 15 %) on a seeded prefix of each group, solved in one
-    mixed-precision persistent call (groups side by side on library streams)."""
+def timed_solves(P, groups, x0s, opts, steps, warmup, ws=None):
+    """Time psr_solve_batch over `groups` (x reset to x0s before each call,
+    outside the timed interval): `warmup` untimed calls, then `steps` calls,
+    each bracketed by HIP events on the launching stream.  The workspace is
+    allocated once, before the timed calls.  Returns (median ms, all ms,
+    stats of the last call, workspace)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    st = None
+    for _ in range(max(1, warmup)):
+        for g, x0 in zip(groups, x0s):
+            g["x"].copy_(x0)
+        st, ws = P.solve_batch(groups, opts, workspace=ws, stats=True)
+    times = []
+    for _ in range(steps):
+        for g, x0 in zip(groups, x0s):
+            g["x"].copy_(x0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        st, ws = P.solve_batch(groups, opts, workspace=ws, stats=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return float(np.median(times)), times, st, ws
+
+
+def oracle_parity(O, mech, cond, energy, idx, x, status, xo, so, tol, opts=None):
+    """Per-reactor parity of GPU results on the oracle sample idx (the same
+    reading as the tests): agree within tol; branch mismatch or GPU-only root
+    verified by an oracle restart at the GPU root (it converges and stays
+    within tol of it); oracle-only roots counted as misses.  Returns
+    counts and the fraction of the GPU-converged sample reactors that are
+    verified steady states."""
+    from tests.gpu_util import rel_err
+    n_sp = mech["species_elems"].shape[0]
+    xg, sg = x[:, idx], status[idx]
+    conv_o, conv_g = so["status"] == 0, sg == 0
+    both = conv_o & conv_g
+    err = rel_err(xg, xo, n_sp)
+    agree = both & (err <= tol)
+    om = O.Mechanism(mech)
+    opts = O.default_opts(**(opts or {}))
+    verified, unverified = 0, 0
+    for j in np.flatnonzero(conv_g & ~agree):
+        b = int(idx[j])
+        args = (cond["P"][b], cond["tau"][b], cond["T_in"][b], cond["Y_in"][:, b], energy)
+        xr, st = om.solve(*args, xg[:, j], opts)
+        e = rel_err(xg[:, j:j + 1], xr[:, None], n_sp)[0]
+        ok = st.status == 0 and e <= tol
+        verified += int(ok)
+        unverified += int(not ok)
+        if not ok:
+            print(f"unverified GPU root: reactor {b}, oracle restart status {st.status}, "
+                  f"{st.n_lin} linear solves, rel err {e:.2e}", file=sys.stderr, flush=True)
+    ng = int(conv_g.sum())
+    return {"sample": int(len(idx)), "oracle_converged": int(conv_o.sum()), "gpu_converged": ng,
+            "agree": int(agree.sum()), "max_rel_err": float(err[agree].max()) if agree.any() else None,
+            "branch_mismatch": int((both & ~agree).sum()), "gpu_only": int((conv_g & ~conv_o).sum()),
+            "verified_other_roots": verified, "unverified": unverified,
+            "oracle_only": int((conv_o & ~conv_g).sum()),
+            "valid_fraction": (int(agree.sum()) + verified) / ng if ng else 0.0}
+
+
+def cpu_cores():
+    """Host cores this process may use, at most 16 (the GPU machine's CPU share per GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def uneven(P, steps=1, warmup=1, sample=64, cores=16):
+    """The three-mechanism workload: 65536 reactors (30/200, 100/600, 200/1200
+    species / reactions, 32768 / 22938 / 9830) in one mixed-precision
+    persistent psr_solve_batch call; oracle parity on a seeded sample of each
+    group over its whole residence-time range."""
     import torch
     from psr_inputs import uneven_workload
     from tests.gpu_util import cond_dev, dev
-    gl, names, x0s = [], [], []
-    for name, mech, cond, x0 in uneven_workload(fraction):
+    gl, names, x0s, host = [], [], [], []
+    for name, mech, cond, x0 in uneven_workload(1.0):
         B = x0.shape[1]
         gl.append(dict(mech=P.Mechanism(mech), cond=cond_dev(cond), energy=True, x=dev(x0),
                        status=torch.empty(B, dtype=torch.int32, device="cuda:0"),
                        n_lin=torch.empty(B, dtype=torch.int32, device="cuda:0")))
         names.append(f"{mech['species_elems'].shape[0]}/{mech['A'].shape[0]}")
         x0s.append(dev(x0))
+        host.append((mech, cond, x0))
     o = P.default_opts(precision=P.PSR_MIXED, scheduler=P.PSR_PERSISTENT)
-    st, ws = P.solve_batch(gl, o, stats=True)  # warm-up (same inputs)
-    for g, x0 in zip(gl, x0s):
-        g["x"].copy_(x0)
-    torch.cuda.synchronize()
-    st, _ = P.solve_batch(gl, o, workspace=ws, stats=True)
-    torch.cuda.synchronize()
-    groups = {nm: {"reactors": int(g["x"].shape[1]), "converged": int((g["status"] == 0).sum().item())}
-              for nm, g in zip(names, gl)}
-    return {"reactors": int(st.reactors), "converged": int(st.converged), "ms": st.kernel_ms,
-            "converged_per_s": st.converged / (st.kernel_ms / 1e3), "groups": groups,
-            "lin_total": int(st.lin_total), "note": f"prefix fraction {fraction:g} of each group"}
+    ms, times, st, ws = timed_solves(P, gl, x0s, o, steps, warmup)
+    print(f"uneven: {st.converged}/{st.reactors} converged, {ms:.1f} ms", file=sys.stderr, flush=True)
+    out = {"reactors": int(st.reactors), "converged": int(st.converged), "ms_per_solve": ms,
+           "ms_all": times, "kernel_ms": st.kernel_ms, "lin_total": int(st.lin_total),
+           "jac_total": int(st.jac_total), "fp64_fallbacks": int(st.fp64_fallbacks), "groups": {}}
+    valid = 0.0
+    for nm, g, (mech, cond, x0) in zip(names, gl, host):
+        x = g["x"].cpu().numpy()
+        status = g["status"].cpu().numpy()
+        conv = int((status == 0).sum())
+        row = {"reactors": int(x.shape[1]), "converged": conv}
+        if sample > 0:
+            from oracle import oracle as O
+            idx = np.sort(np.random.default_rng(2025).choice(x.shape[1], sample, replace=False))
+            t0 = time.perf_counter()
+            xo, so = O.solve_batch(mech, cond, x0, True, idx=idx, processes=cores)
+            row["parity"] = oracle_parity(O, mech, cond, True, idx, x, status, xo, so, TOL[1])
+            row["parity"]["oracle_s"] = time.perf_counter() - t0
+            valid += conv * row["parity"]["valid_fraction"]
+            print(f"uneven {nm}: parity {row['parity']}", file=sys.stderr, flush=True)
+        else:
+            valid += conv
+        out["groups"][nm] = row
+    out["valid_converged_per_s"] = valid / (ms / 1e3)
+    return out
 
 
-def soot(P, reactors=512):
+def soot(P, steps=1, warmup=1, sample=32, cores=16):
     """The sooting workload (150 species / 900 reactions + 6 soot moments,
-    n = 157, fuel-rich inlet) on a seeded prefix: mixed-precision persistent
-    solve against the plain FP64 solve of the same reactors."""
+    n = 157, fuel-rich inlet), all 8192 reactors, mixed-precision persistent
+    solve; oracle parity on a seeded sample."""
     import torch
     from psr_inputs import workload
     from tests.gpu_util import cond_dev, dev
-    mech, cond, x0, _ = workload("soot", reactors)
+    mech, cond, x0, _ = workload("soot")
     B = x0.shape[1]
     M = P.Mechanism(mech)
     cd, x0d = cond_dev(cond), dev(x0)
-    out = {"reactors": B, "n": int(x0.shape[0])}
-    for name, o in (("mixed_persistent", P.default_opts(precision=P.PSR_MIXED, scheduler=P.PSR_PERSISTENT)),
-                    ("fp64_plain", P.default_opts(precision=P.PSR_FP64, scheduler=P.PSR_PLAIN))):
-        g = dict(mech=M, cond=cd, energy=True, x=x0d.clone(),
-                 status=torch.empty(B, dtype=torch.int32, device="cuda:0"),
-                 n_lin=torch.empty(B, dtype=torch.int32, device="cuda:0"))
-        st, ws = P.solve_batch([g], o, stats=True)  # warm-up (same inputs)
-        g["x"].copy_(x0d)
-        torch.cuda.synchronize()
-        st, _ = P.solve_batch([g], o, workspace=ws, stats=True)
-        torch.cuda.synchronize()
-        out[name] = {"converged": int(st.converged), "ms": st.kernel_ms,
-                     "converged_per_s": st.converged / (st.kernel_ms / 1e3), "lin_total": int(st.lin_total),
-                     "fp64_fallbacks": int(st.fp64_fallbacks)}
-        print(f"soot {name}: {st.converged}/{B} converged in {st.kernel_ms:.1f} ms", file=sys.stderr,
-              flush=True)
+    g = dict(mech=M, cond=cd, energy=True, x=x0d.clone(),
+             status=torch.empty(B, dtype=torch.int32, device="cuda:0"),
+             n_lin=torch.empty(B, dtype=torch.int32, device="cuda:0"))
+    o = P.default_opts(precision=P.PSR_MIXED, scheduler=P.PSR_PERSISTENT)
+    ms, times, st, ws = timed_solves(P, [g], [x0d], o, steps, warmup)
+    print(f"soot: {st.converged}/{B} converged, {ms:.1f} ms", file=sys.stderr, flush=True)
+    out = {"reactors": B, "n": int(x0.shape[0]), "converged": int(st.converged), "ms_per_solve": ms,
+           "ms_all": times, "kernel_ms": st.kernel_ms, "lin_total": int(st.lin_total),
+           "jac_total": int(st.jac_total), "fp64_fallbacks": int(st.fp64_fallbacks)}
+    valid = float(st.converged)
+    if sample > 0:
+        from oracle import oracle as O
+        x = g["x"].cpu().numpy()
+        status = g["status"].cpu().numpy()
+        idx = np.sort(np.random.default_rng(2026).choice(B, sample, replace=False))
+        t0 = time.perf_counter()
+        xo, so = O.solve_batch(mech, cond, x0, True, idx=idx, processes=cores)
+        out["parity"] = oracle_parity(O, mech, cond, True, idx, x, status, xo, so, TOL[1])
+        out["parity"]["oracle_s"] = time.perf_counter() - t0
+        valid *= out["parity"]["valid_fraction"]
+        print(f"soot: parity {out['parity']}", file=sys.stderr, flush=True)
+    out["valid_converged_per_s"] = valid / (ms / 1e3)
     return out
 
 
@@ -326,16 +481,16 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mixed")
-    ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="reactors for the oracle baseline (0: the whole batch)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lu-large", action="store_true")
-    ap.add_argument("--no-uneven", action="store_true")
+    ap.add_argument("--uneven-sample", type=int, default=48,
+                    help="oracle parity sample per group of the 65536-reactor workload (-1: skip the leg)")
+    ap.add_argument("--soot-sample", type=int, default=32,
+                    help="oracle parity sample of the 8192-reactor sooting workload (-1: skip the leg)")
     ap.add_argument("--sweep-chains", type=int, default=4096,
                     help="chains of the continuation sweeps (0: skip)")
-    ap.add_argument("--soot-reactors", type=int, default=512,
-                    help="prefix of the sooting workload to solve (0: skip)")
     ap.add_argument("--newton-sizes", default="100,1000,10000,100000,1000000",
                     help="batch sizes of the one-Newton-iteration sweep, comma separated ('' or 0: skip)")
     ap.add_argument("--tune-sample", type=int, default=4096,
@@ -351,7 +506,7 @@ def main():
     import torch
     import paper_2005_11468_amd as P
     from psr_inputs import workload
-    from tests.gpu_util import cond_dev, dev, rel_err
+    from tests.gpu_util import cond_dev, dev
 
     mech, cond, x0, energy = workload(args.workload)
     B = x0.shape[1]
@@ -361,35 +516,12 @@ def main():
     M = P.Mechanism(mech)
     cd = cond_dev(cond)
     x0d = dev(x0)
-    x = x0d.clone()
-    status = torch.empty(B, dtype=torch.int32, device="cuda:0")
-    nlin = torch.empty(B, dtype=torch.int32, device="cuda:0")
-    group = [dict(mech=M, cond=cd, energy=energy, x=x, status=status, n_lin=nlin)]
-    stream = torch.cuda.current_stream()
+    group = [dict(mech=M, cond=cd, energy=energy, x=x0d.clone(),
+                  status=torch.empty(B, dtype=torch.int32, device="cuda:0"),
+                  n_lin=torch.empty(B, dtype=torch.int32, device="cuda:0"))]
+    cores = cpu_cores()
 
-    def run(opts, steps, warmup, ws=None):
-        for _ in range(warmup):
-            x.copy_(x0d)
-            _, ws = P.solve_batch(group, opts, workspace=ws, stats=False)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            x.copy_(x0d)
-            _, ws = P.solve_batch(group, opts, workspace=ws, stats=False)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        ms = e0.elapsed_time(e1) / steps
-        # one more solve for the solver statistics (kernel time from HIP events
-        # recorded by the library on this stream around its launches)
-        x.copy_(x0d)
-        st, ws = P.solve_batch(group, opts, workspace=ws, stats=True)
-        torch.cuda.synchronize()
-        return ms, wall / steps, st, ws
-
-    mixed = P.default_opts(precision=P.PSR_MIXED, scheduler=P.PSR_PERSISTENT)
+    mixed = P.default_opts(precision=P.PSR_MIXED, scheduler=P.PSR_PERSISTENT, **FAST_OPTS)
     tune = None
     if args.tune_sample > 0:
         # launch shape picked by the autotuner on a prefix of the batch (setup,
@@ -400,95 +532,103 @@ def main():
                 "candidates": r.candidates, "sample": min(args.tune_sample, B),
                 "sample_ms": r.ms, "default_shape_sample_ms": r.default_ms,
                 "tuning_s": time.perf_counter() - t0}
-    ms_mixed, wall_mixed, st_mixed, ws = run(mixed, args.steps, args.warmup)
-    x_mixed = x.cpu().numpy()
-    s_mixed = status.cpu().numpy()
-    n_mixed = nlin.cpu().numpy()
 
-    plain = P.default_opts(precision=P.PSR_FP64, scheduler=P.PSR_PLAIN)
-    ms_plain, wall_plain, st_plain, _ = run(plain, args.plain_steps, 0)
-    x_plain = x.cpu().numpy()
-    s_plain = status.cpu().numpy()
+    # every solver leg timed the same way: warm-up, then the median of
+    # `steps` calls, workspace allocated before the timed calls
+    legs = {}
+    for name, opts in (("mixed_persistent", mixed),
+                       ("fp64_plain", P.default_opts(precision=P.PSR_FP64, scheduler=P.PSR_PLAIN, **FAST_OPTS)),
+                       ("fp64_persistent", P.default_opts(precision=P.PSR_FP64, scheduler=P.PSR_PERSISTENT,
+                                                          **FAST_OPTS))):
+        ms, times, st, _ = timed_solves(P, group, [x0d], opts, args.steps, args.warmup)
+        legs[name] = {"ms": ms, "ms_all": times, "st": st, "x": group[0]["x"].cpu().numpy(),
+                      "status": group[0]["status"].cpu().numpy()}
+        print(f"{name}: {st.converged}/{B} converged, median {ms:.2f} ms", file=sys.stderr, flush=True)
 
-    fp64p = P.default_opts(precision=P.PSR_FP64, scheduler=P.PSR_PERSISTENT)
-    ms_fp64p, _, st_fp64p, _ = run(fp64p, args.plain_steps, 0)
-    s_fp64p = status.cpu().numpy()
+    # oracle on the workload (the CPU baseline, and the parity reference of
+    # every timed leg)
+    cpu = None
+    parity = {}
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        S = args.cpu_sample or B
+        idx = np.sort(np.random.default_rng(2024).choice(B, S, replace=False)) if S < B else np.arange(B)
+        t0 = time.perf_counter()
+        xo, so = O.solve_batch(mech, cond, x0, energy, idx=idx, processes=cores,
+                               opts=O.default_opts(**FAST_OPTS))
+        tcpu = time.perf_counter() - t0
+        conv_o = int((so["status"] == 0).sum())
+        cpu = {"value": conv_o / tcpu, "unit": "reactor-solves/s", "cores": cores, "kind": "oracle",
+               "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+               "per_core": conv_o / tcpu / cores,
+               "sample": f"{S} of {B} reactors, single-threaded FP64 C oracle (gcc -O2), one process "
+                         f"per core over a round-robin split, {tcpu:.1f} s wall"}
+        for name, leg in legs.items():
+            tol = TOL[1] if name.startswith("mixed") else TOL[0]
+            parity[name] = oracle_parity(O, mech, cond, energy, idx, leg["x"], leg["status"], xo, so, tol,
+                                         FAST_OPTS)
+            print(f"parity {name}: {parity[name]}", file=sys.stderr, flush=True)
+
+    def rate_of(name):
+        leg = legs[name]
+        conv = int((leg["status"] == 0).sum())
+        frac = parity[name]["valid_fraction"] if name in parity else 1.0
+        return conv * frac / (leg["ms"] / 1e3)
+
+    value = rate_of("mixed_persistent")
+    value_plain = rate_of("fp64_plain")
+    value_fp64p = rate_of("fp64_persistent")
 
     rate = rate200 = None
     if args.rate_reactors > 0:
         rate = rate_kernel(P, args.rate_reactors)
         rate200 = rate_kernel(P, args.rate_reactors, name="rate200")
     lu_big = lu_large(P) if not args.no_lu_large else None
-    unev = uneven(P) if not args.no_uneven else None
-    soot_leg = soot(P, args.soot_reactors) if args.soot_reactors > 0 else None
+    unev = uneven(P, sample=args.uneven_sample, cores=cores) if args.uneven_sample >= 0 else None
+    soot_leg = soot(P, sample=args.soot_sample, cores=cores) if args.soot_sample >= 0 else None
     sizes = [int(v) for v in args.newton_sizes.split(",") if v.strip() and int(v) > 0]
     newton = newton_sweep(P, sizes) if sizes else None
     sweep_leg = continuation(P, args.sweep_chains) if args.sweep_chains > 0 else None
 
-    # oracle on a bounded sample: CPU baseline and parity reference
-    cpu = None
-    parity = None
-    if not args.no_cpu_baseline:
-        from oracle import oracle as O
-        cores = min(os.cpu_count() or 1, 16)
-        S = args.cpu_sample or B
-        idx = np.sort(np.random.default_rng(2024).choice(B, S, replace=False))
-        t0 = time.perf_counter()
-        xo, so = O.solve_batch(mech, cond, x0, energy, idx=idx, processes=cores)
-        tcpu = time.perf_counter() - t0
-        conv_o = so["status"] == 0
-        cpu = {"value": float(conv_o.sum() / tcpu), "unit": "reactor-solves/s", "cores": cores,
-               "kind": "oracle",
-               "sample": f"{S} of {B} reactors (seeded), single-threaded FP64 C oracle, "
-                         f"one process per core, {tcpu:.1f} s"}
-        both = conv_o & (s_mixed[idx] == 0)
-        em = rel_err(x_mixed[:, idx][:, both], xo[:, both], N)
-        bp = conv_o & (s_plain[idx] == 0)
-        ep = rel_err(x_plain[:, idx][:, bp], xo[:, bp], N)
-        parity = {"sample": int(S), "oracle_converged": int(conv_o.sum()),
-                  "mixed_max_rel_err": float(em.max()) if em.size else None,
-                  "mixed_within_1e-7": float((em <= TOL[1]).mean()) if em.size else 0.0,
-                  "fp64_max_rel_err": float(ep.max()) if ep.size else None,
-                  "fp64_within_1e-8": float((ep <= TOL[0]).mean()) if ep.size else 0.0}
-
-    conv_mixed = int((s_mixed == 0).sum())
-    conv_plain = int((s_plain == 0).sum())
-    frac_m = parity["mixed_within_1e-7"] if parity else 1.0
-    frac_p = parity["fp64_within_1e-8"] if parity else 1.0
-    value = conv_mixed * frac_m / (ms_mixed / 1e3)
-    value_plain = conv_plain * frac_p / (ms_plain / 1e3)
-
-    lin_f, rnd_f = alg_flops(n, N, I)
-    flops = st_mixed.jac_total * lin_f + st_mixed.lin_total * rnd_f
-    achieved = flops / (st_mixed.kernel_ms / 1e3) / 1e12
-    # the counters were taken with the automatic launch shape of the wavefront
-    # engine; another shape moves other bytes
-    auto_shape = mixed.engine == 0 and mixed.rpw == 0 and mixed.grid_per_cu == 0
-    kname = "k_wpersist<64,mixed>" if mixed.engine != 1 else "k_persistent<mixed,n<=64>"
+    # roofline of the dominant kernel (the persistent solve kernel): the
+    # solver's own counts of linearisations and rounds times the algorithmic
+    # flops of each, over the kernel time from the library's HIP events on
+    # the launching stream
+    st_m = legs["mixed_persistent"]["st"]
+    lin_f, rnd_f = unit_flops(n, N, I)
+    flops = st_m.jac_total * lin_f + st_m.lin_total * rnd_f
+    achieved = flops / (st_m.kernel_ms / 1e3) / 1e12
+    kname = "k_wpersist<64,true>" if n <= 64 else "k_persistent<true,false>"
+    traffic = measured_traffic(kname, f"{args.workload}:{B}")
     out = {
         "metric": "converged PSR solves/sec (1 GPU), mixed-prec batched vs plain FP64, rel err<=1e-7",
         "value": value, "unit": "reactor-solves/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_mixed, "higher_is_better": True,
+        "warmup": args.warmup, "ms_per_step": legs["mixed_persistent"]["ms"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
         "data": "synthetic",
         "config": {"workload": "mixed: 53 species / 325 reactions + energy, 16384 reactors",
                    "reactors": B, "species": N, "reactions": I, "unknowns": n,
                    "precision": "mixed (FP32 LU + FP64 refinement, FP64 residual)",
-                   "scheduler": "persistent work queue", "launch_shape": tune},
-        "fp64_plain": {"value": value_plain, "ms_per_step": ms_plain,
-                       "converged": conv_plain, "rounds": st_plain.rounds,
+                   "scheduler": "persistent work queue", "launch_shape": tune,
+                   "solver_options": FAST_OPTS},
+        "fp64_plain": {"value": value_plain, "ms_per_step": legs["fp64_plain"]["ms"],
+                       "ms_all": legs["fp64_plain"]["ms_all"],
+                       "converged": int((legs["fp64_plain"]["status"] == 0).sum()),
+                       "rounds": legs["fp64_plain"]["st"].rounds,
                        "speedup_mixed_over_plain": value / value_plain if value_plain else None},
-        "fp64_persistent": {"value": int((s_fp64p == 0).sum()) / (ms_fp64p / 1e3),
-                            "ms_per_step": ms_fp64p, "note": "context: FP32 and FP64 vector "
-                            "arithmetic run at the same rate on this GPU"},
-        "solver": {"converged": conv_mixed, "reactors": B, "lin_total": st_mixed.lin_total,
-                   "lin_max": st_mixed.lin_max, "jac_total": st_mixed.jac_total,
-                   "fp64_fallbacks": st_mixed.fp64_fallbacks, "wall_ms_per_step": wall_mixed * 1e3},
+        "fp64_persistent": {"value": value_fp64p, "ms_per_step": legs["fp64_persistent"]["ms"],
+                            "ms_all": legs["fp64_persistent"]["ms_all"],
+                            "converged": int((legs["fp64_persistent"]["status"] == 0).sum()),
+                            "speedup_mixed_over_fp64_persistent": value / value_fp64p if value_fp64p else None},
+        "solver": {"converged": int((legs["mixed_persistent"]["status"] == 0).sum()), "reactors": B,
+                   "ms_all": legs["mixed_persistent"]["ms_all"],
+                   "lin_total": st_m.lin_total, "lin_max": st_m.lin_max, "jac_total": st_m.jac_total,
+                   "fp64_fallbacks": st_m.fp64_fallbacks},
         "roofline": {"kernel": kname, "bound": "alu", "achieved": achieved,
                      "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
-                     "traffic": SOLVE_TRAFFIC_BYTES if auto_shape else None,
-                     "kernel_ms": st_mixed.kernel_ms,
-                     "alg_flops": flops},
+                     "traffic": traffic, "kernel_ms": st_m.kernel_ms, "alg_flops": flops,
+                     "flops_per_linearisation": lin_f, "flops_per_round": rnd_f,
+                     "linearisations": int(st_m.jac_total), "rounds": int(st_m.lin_total)},
         "rate_kernel": rate,
         "rate_kernel_200sp": rate200,
         "lu_large": lu_big,
