@@ -154,6 +154,21 @@ psr_status psr_jacobian(psr_mech_t mech, const psr_conditions *cond, const doubl
 psr_status psr_jacobian_fd(psr_mech_t mech, const psr_conditions *cond, const double *x, double *J,
                            double *work, void *stream);
 
+/* psr_jacobian_fd for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels, with the 3 n B work doubles in a static device array of
+ * 4 Mi doubles (32 MiB) that each device the library runs on holds until the
+ * process ends.  The call allocates nothing (no hipMalloc, hipFree or other
+ * allocating routine); the first call on a device looks up that array's
+ * address for the device.  Errors: those of psr_jacobian_fd, PSR_EINVAL for
+ * a null x or J and when 3 n B exceeds 4194304 (nothing is launched then),
+ * PSR_EDEVICE if the address lookup fails.  Every call on one device shares
+ * that device's array and its contents are undefined after a call: calls
+ * whose launches overlap on one device (two streams, two host threads) race
+ * and give wrong Jacobians; serialise them. */
+psr_status psr_jacobian_fd_noalloc(psr_mech_t mech, const psr_conditions *cond, const double *x, double *J,
+                                   void *stream);
+
 /* Batched LU with partial pivoting of B independent n x n row-major
  * matrices (device [B][n][n], overwritten by L\U with unit-lower L), pivots
  * device [B][n] (LAPACK convention: row k was swapped with row piv[k]),

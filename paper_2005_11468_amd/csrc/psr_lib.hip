@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "../../include/psr.h"
@@ -900,6 +901,61 @@ extern "C" psr_status psr_jacobian_fd(psr_mech_t m, const psr_conditions *c, con
     HIP_OK(hipGetLastError());
   }
   return PSR_OK;
+}
+
+// ------------------------------------------- allocation-free FD Jacobian
+
+// Scratch of psr_jacobian_fd_noalloc: the three n x B work arrays of the
+// finite-difference Jacobian (F(x), F at the perturbed state, the perturbed
+// state) live in this file-scope device array, one copy per device, held
+// until the process ends.  Host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kFdScratchDoubles = (size_t)4 << 20;  // 4 Mi doubles, 32 MiB per device
+static __device__ __align__(256) double scratch[kFdScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+
+// Device address of `scratch` on the current device, looked up once per
+// device (the device current during the lookup) and kept.
+static psr_status scratch_address(double **out) {
+  static std::mutex mu;
+  static double *addr[kMaxDevices] = {};
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(PSR_EUNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      char msg[160];
+      snprintf(msg, sizeof msg, "hipGetSymbolAddress of the FD scratch failed: %s", hipGetErrorString(e));
+      return fail(PSR_EDEVICE, msg);
+    }
+    addr[dev] = static_cast<double *>(p);
+  }
+  *out = addr[dev];
+  return PSR_OK;
+}
+
+extern "C" psr_status psr_jacobian_fd_noalloc(psr_mech_t m, const psr_conditions *c, const double *x,
+                                              double *J, void *stream) {
+  psr_status st = check_cond(m, c);
+  if (st != PSR_OK) return st;
+  if (!x || !J) return fail(PSR_EINVAL, "null x or J");
+  const int n = n_unknowns(m->dev, c->energy);
+  const size_t need = 3 * (size_t)n * (size_t)c->n_reactors;
+  if (need > kFdScratchDoubles) {
+    char msg[200];
+    snprintf(msg, sizeof msg,
+             "3 n B = %zu doubles exceeds the %zu-double scratch of psr_jacobian_fd_noalloc "
+             "(use psr_jacobian_fd with a caller-owned work buffer)", need, kFdScratchDoubles);
+    return fail(PSR_EINVAL, msg);
+  }
+  double *work = nullptr;
+  st = scratch_address(&work);
+  if (st != PSR_OK) return st;
+  return psr_jacobian_fd(m, c, x, J, work, stream);
 }
 
 // Device scratch of the large-matrix LU entry point, grown on demand and kept
