@@ -293,7 +293,7 @@ psr_status psr_solve_batch(const psr_group *groups, int32_t n_groups, const psr_
 /* Parameter a continuation sweep varies. */
 enum { PSR_SWEEP_T_IN = 0, PSR_SWEEP_TAU = 1 };
 
-/* Continuation sweep (paper Section 4: steady solutions followed along the
+/* Continuation sweep (paper Section 5: steady solutions followed along the
  * reactor temperature at a fixed residence time, and along the residence
  * time at a fixed temperature, each solution started from the one before).
  * group: one mechanism's B reactors, each the start of its own chain.  At

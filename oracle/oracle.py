@@ -336,7 +336,7 @@ def solve_batch(mech: dict, cond: dict, x0: np.ndarray, energy: bool, *, idx=Non
 
 def sweep_batch(mech: dict, cond: dict, x0: np.ndarray, energy: bool, param: str,
                 values: np.ndarray, *, opts: Opts | None = None, processes: int = 1):
-    """Continuation sweep (paper Section 4: steady solutions followed along
+    """Continuation sweep (paper Section 5: steady solutions followed along
     one condition, each started from the solution before).  At step k the
     condition `param` ("T_in" or "tau") of reactor b is values[k, b]; the
     initial guess of step k is the state step k-1 left (x0 at step 0).

@@ -132,7 +132,7 @@ def subset(cond: dict, x0: np.ndarray, idx) -> tuple[dict, np.ndarray]:
             np.ascontiguousarray(x0[:, idx]))
 
 
-# Continuation sweeps of the paper's validation protocol (Section 4), run on
+# Continuation sweeps of the paper's validation protocol (Section 5), run on
 # isothermal reactors of the 53-species mechanism with the phi inlet:
 # temperature 1500 -> 2000 K in 50 K steps at tau = 5 ms, and residence time
 # 5 -> 95 ms in 5 ms steps at 1750 K.  Every reactor of the batch is its own

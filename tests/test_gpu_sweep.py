@@ -1,5 +1,5 @@
 """GPU parity of the continuation sweep (psr_sweep_batch, called through the
-C ABI): the paper's Section 4 protocol -- temperature 1500 -> 2000 K at
+C ABI): the paper's Section 5 protocol -- temperature 1500 -> 2000 K at
 tau = 5 ms and residence time 5 -> 95 ms at 1750 K, every step started from
 the step before -- on isothermal reactors of the 53-species mechanism, each
 reactor its own chain.  Every step's state is compared with the oracle's own

@@ -165,3 +165,26 @@ def test_converged_root_invariants(oracle_mod, soot_mech, consts):
         Cc, _, _ = O.production(T, P, Y)
         R, W, G, _ = O.soot_sources(T, Cc[m2["soot"]["precursor"]], Cc[m2["soot"]["growth"]], lnM)
         assert np.allclose(np.exp(lnM), tau * R, rtol=1e-10)
+
+
+def test_monodisperse_sources_absolute(oracle_mod, soot_mech):
+    """Absolute source values at T = 1700 K for a monodisperse population
+    (M_0 = 2e9 cm^-3, m = 40 carbon atoms) from the published formulas, the
+    numbers worked out separately (double precision, constants: N_A =
+    6.02214076e23 /mol, k_B = 1.380649e-16 erg/K, R = 8.314462618 J/mol/K,
+    m_C = 12.011 g/mol / N_A, rho_s = 1.8 g/cm^3, chi = 2.3e15 /cm^2):
+      K_f = 2.2 (3 m_C / (4 pi rho_s))^(1/6) (6 k_B T / rho_s)^(1/2)
+          = 2.2884390353e-10 cm^3/s,
+      G_0 = -(1/2) K_f M_0^2 f_00, f_00 = 4 sqrt(2) m^(1/6)
+          = -4.78800208182e9 /(cm^3 s),
+      W_1 = k_s [G] chi pi d_C^2 M_0 D m^(2/3), d_C = (6 m_C / (pi rho_s))^(1/3)
+          = 2.7660012947e-8 cm, k_s = 1e9 exp(-4e4 / (R T)), [G] = 2e-8 mol/cm^3,
+          D = 2: W_1 = 3.05271381607e11 /(cm^3 s),
+      R_0 = N_A k_n [P]^2, k_n = 1e9 exp(-5e4 / (R T)), [P] = 3e-9 mol/cm^3:
+          R_0 = 1.57655986748e14 /(cm^3 s).
+    A wrong exponent, a missing pi or factor 2 in any prefactor fails."""
+    O = oracle_mod.Mechanism(soot_mech)
+    R, W, G, sk = O.soot_sources(1700.0, 3e-9, 2e-8, _mono_lnM(2e9, 40.0))
+    assert G[0] == pytest.approx(-4.78800208182457e9, rel=1e-11)
+    assert W[1] == pytest.approx(3.052713816068612e11, rel=1e-11)
+    assert R[0] == pytest.approx(1.5765598674782403e14, rel=1e-11)

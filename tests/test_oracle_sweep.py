@@ -1,4 +1,4 @@
-"""Pins of the oracle's continuation sweep (paper Section 4: steady solutions
+"""Pins of the oracle's continuation sweep (paper Section 5: steady solutions
 followed along the reactor temperature, then along the residence time, each
 started from the solution before).  The pins do not rest on the oracle's own
 solver: every converged step must (1) conserve each element between inlet
