@@ -309,8 +309,11 @@ def timed_solves(P, groups, x0s, opts, steps, warmup, ws=None):
 def oracle_parity(O, mech, cond, energy, idx, x, status, xo, so, tol, opts=None):
     """Per-reactor parity of GPU results on the oracle sample idx (the same
     reading as the tests): agree within tol; branch mismatch or GPU-only root
-    verified by an oracle restart at the GPU root (it converges and stays
-    within tol of it); oracle-only roots counted as misses.  Returns
+    verified by an oracle restart at the GPU root: it converges, either with
+    its first linear solve (the oracle's own convergence test accepts the
+    GPU root; trace species may then differ by up to the step-norm weight
+    atol_Y + rtol |Y|) or to within tol of the GPU root; oracle-only roots
+    counted as misses.  Returns
     counts and the fraction of the GPU-converged sample reactors that are
     verified steady states."""
     from tests.gpu_util import rel_err
@@ -328,7 +331,7 @@ def oracle_parity(O, mech, cond, energy, idx, x, status, xo, so, tol, opts=None)
         args = (cond["P"][b], cond["tau"][b], cond["T_in"][b], cond["Y_in"][:, b], energy)
         xr, st = om.solve(*args, xg[:, j], opts)
         e = rel_err(xg[:, j:j + 1], xr[:, None], n_sp)[0]
-        ok = st.status == 0 and e <= tol
+        ok = st.status == 0 and (st.n_lin <= 1 or e <= tol)
         verified += int(ok)
         unverified += int(not ok)
         if not ok:
@@ -497,6 +500,9 @@ def main():
                     help="reactors the autotuner times each launch shape on (0: automatic shape)")
     ap.add_argument("--rate-reactors", type=int, default=1_000_000,
                     help="batch size of the residual-kernel measurement (0: skip)")
+    ap.add_argument("--only-legs", action="store_true",
+                    help="profiling runs: skip the headline solver legs and the oracle, print only "
+                         "the other legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus must be 1",
@@ -507,6 +513,12 @@ def main():
     import paper_2005_11468_amd as P
     from psr_inputs import workload
     from tests.gpu_util import cond_dev, dev
+
+    if args.only_legs:
+        out = {"rate_kernel": rate_kernel(P, args.rate_reactors) if args.rate_reactors > 0 else None,
+               "lu_large": lu_large(P) if not args.no_lu_large else None}
+        print(json.dumps(out))
+        return
 
     mech, cond, x0, energy = workload(args.workload)
     B = x0.shape[1]

@@ -46,7 +46,9 @@ enum {
   PSR_R_CONVERGED = 0, /* root found: weighted Newton step <= 1 and scaled residual <= ftol */
   PSR_R_MAXITER = 1,   /* linear-solve budget spent                                         */
   PSR_R_TS_FAILED = 2, /* pseudo-transient step size fell below h_min                        */
-  PSR_R_NONFINITE = 3  /* converged iterate not finite                                       */
+  PSR_R_NONFINITE = 3, /* converged iterate not finite                                       */
+  PSR_R_SINGULAR = 4   /* pseudo-transient step size fell below h_min after a step rejected
+                          because its matrix had no nonzero pivot                          */
 };
 
 enum { PSR_FP64 = 0, PSR_MIXED = 1 };        /* precision of the LU factorisation */
@@ -175,7 +177,12 @@ psr_status psr_jacobian_fd_noalloc(psr_mech_t mech, const psr_conditions *cond, 
  * info device [B] (0, or k+1 if column k had no nonzero pivot).
  * precision PSR_FP64 factors in double; PSR_MIXED rounds each matrix to
  * float, factors in float and writes the float factors back as double.
- * Asynchronous.                                                             */
+ * Asynchronous.  For PSR_MIXED with 64 < n <= 256 the factorisation works
+ * in a library-owned device buffer, one per (device, stream) pair, allocated
+ * on the first such call and grown on demand (that call synchronises the
+ * stream before freeing the smaller buffer); calls on one stream are ordered
+ * and calls on different streams use different buffers, so concurrent calls
+ * on different streams or host threads do not share scratch memory. */
 psr_status psr_lu_factor_batch(int32_t n, int64_t batch, int32_t precision, double *A, int32_t *piv,
                                int32_t *info, void *stream);
 

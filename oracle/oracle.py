@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 SOURCES = ["psr_oracle.c"]
 DEPENDS = ["psr_oracle.c", "psr_oracle.h", "residual_body.inc"]
 
-STATUS = {0: "CONVERGED", 1: "MAXITER", 2: "TS_FAILED", 3: "NONFINITE"}
+STATUS = {0: "CONVERGED", 1: "MAXITER", 2: "TS_FAILED", 3: "NONFINITE", 4: "SINGULAR"}
 
 
 def build(force: bool = True) -> str:

@@ -584,7 +584,7 @@ done:
   return result;
 }
 
-enum { TS_ACCEPTED, TS_REJECTED, TS_BUDGET };
+enum { TS_ACCEPTED, TS_REJECTED, TS_SINGULAR, TS_BUDGET };
 
 /* One pseudo-transient step of M dx/dt = -F(x) (M: the mass-matrix
  * diagonal frozen at x) with the two-stage L-stable Rosenbrock method ROS2
@@ -599,7 +599,8 @@ enum { TS_ACCEPTED, TS_REJECTED, TS_BUDGET };
  * changes are relative changes of M_r already), x_new is finite, T stays in [T_min, T_max] and no
  * mass fraction is below -ts_neg_tol; negative mass fractions are then set
  * to zero.  h is rescaled by 0.9/sqrt(err) within [0.2, 5] (0.25 after a
- * non-finite or out-of-bounds result).  Counts two linear solves.        */
+ * non-finite or out-of-bounds result).  Counts two linear solves.  Returns
+ * TS_SINGULAR for a step rejected because A had no nonzero pivot.        */
 static int ros2_step(const om_mech *m, const om_cond *c, const om_opts *o, double *x, double *h,
                      om_stats *st)
 {
@@ -620,8 +621,12 @@ static int ros2_step(const om_mech *m, const om_cond *c, const om_opts *o, doubl
   om_mass_diag(m, c, x, M);
   st->n_jac++;
   for (int i = 0; i < n; i++) A[(size_t)i * n + i] += M[i] / (gam * hh);
-  if (!all_finite(n, F) || !all_finite(n * n, A) || eq_factor(n, A, piv, rs, cs) != 0) {
+  int sing = 0;
+  if (!all_finite(n, F) || !all_finite(n * n, A)) {
     bad = 1;
+  } else if (eq_factor(n, A, piv, rs, cs) != 0) {
+    bad = 1;
+    sing = 1;
   } else {
     for (int i = 0; i < n; i++) k1[i] = -F[i] / (gam * hh);
     eq_solve(n, A, piv, rs, cs, k1);
@@ -658,6 +663,7 @@ static int ros2_step(const om_mech *m, const om_cond *c, const om_opts *o, doubl
   } else {
     double fac = bad ? 0.25 : 0.9 / sqrt(err);
     *h = hh * (fac < 0.2 ? 0.2 : fac);
+    if (sing) result = TS_SINGULAR;
   }
   free(F); free(A); free(M); free(k1); free(k2); free(x1); free(xn); free(piv); free(rs); free(cs);
   return result;
@@ -751,7 +757,7 @@ int om_solve(const om_mech *m, const om_cond *c, const om_opts *o, double *x, om
       st->n_ts++;
       if (accepted % o->nw_every == 0 && h >= o->nw_h_ratio * c->tau) attempt = 1;
     } else if (h < o->h_min) {
-      st->status = OM_TS_FAILED;
+      st->status = r == TS_SINGULAR ? OM_SINGULAR : OM_TS_FAILED;
       break;
     }
   }
@@ -772,7 +778,7 @@ int om_time_march_only(const om_mech *m, const om_cond *c, const om_opts *o, dou
     int r = ros2_step(m, c, o, x, &h, st);
     if (r == TS_BUDGET) { st->status = OM_MAXITER; break; }
     if (r == TS_ACCEPTED) st->n_ts++;
-    else if (h < o->h_min) { st->status = OM_TS_FAILED; break; }
+    else if (h < o->h_min) { st->status = r == TS_SINGULAR ? OM_SINGULAR : OM_TS_FAILED; break; }
   }
   return st->status;
 }

@@ -93,7 +93,7 @@ typedef struct {
   double ct_min_step;          /* smallest step in ln tau before giving up     */
 } om_opts;
 
-enum { OM_CONVERGED = 0, OM_MAXITER = 1, OM_TS_FAILED = 2, OM_NONFINITE = 3 };
+enum { OM_CONVERGED = 0, OM_MAXITER = 1, OM_TS_FAILED = 2, OM_NONFINITE = 3, OM_SINGULAR = 4 };
 
 typedef struct {
   int status;

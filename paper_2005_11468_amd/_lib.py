@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(HERE, "libpsr.so")
 PSR_OK, PSR_EINVAL, PSR_ENOMEM, PSR_EDEVICE, PSR_EUNSUPPORTED = 0, 1, 2, 3, 4
 PSR_FP64, PSR_MIXED = 0, 1
 PSR_PLAIN, PSR_PERSISTENT = 0, 1
-STATUS_NAMES = {0: "CONVERGED", 1: "MAXITER", 2: "TS_FAILED", 3: "NONFINITE"}
+STATUS_NAMES = {0: "CONVERGED", 1: "MAXITER", 2: "TS_FAILED", 3: "NONFINITE", 4: "SINGULAR"}
 
 dp, ip, vp = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_void_p
 

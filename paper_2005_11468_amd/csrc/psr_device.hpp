@@ -64,16 +64,23 @@ struct Opts {
 // Mixed precision: refinement target of the solve whose Newton step ends a
 // reactor's solve (the loose opts.refine_tol only steers the iteration).
 constexpr double kFinalRefine = 1e-10;
-// Mixed precision: after a matrix needed the FP64 fallback, this many
-// following linearisations of the reactor are factored in FP64 directly (the
-// float attempt on a matrix that ill-conditioned would be wasted).
+// Mixed precision: after a matrix needed the FP64 fallback, the following
+// linearisations of the reactor are factored in FP64 directly (the float
+// attempt on a matrix that ill-conditioned would be wasted): kStickFP64 of
+// them after a first fallback, twice as many after each further fallback of
+// a float attempt (up to kStickMax), back to none once a float attempt goes
+// through without one.  The FP32 factors only help while cond(A) stays well
+// below 1 / eps_float; the Jacobians of the 100- to 201-unknown mechanisms
+// often do not.
 constexpr int kStickFP64 = 4;
+constexpr int kStickMax = 256;
 
 enum Phase : int { PH_NW_BASE = 0, PH_NW_TRIAL = 1, PH_TS1 = 2, PH_TS2 = 3, PH_DONE = 4 };
 // Continuation in tau: first attempt at the reactor's tau, down search,
 // walk back up, or not (any more) in use.
 enum CtMode : int { CT_OFF = 0, CT_FIRST = 1, CT_DOWN = 2, CT_WALK = 3 };
-enum RStatus : int { RS_CONVERGED = 0, RS_MAXITER = 1, RS_TS_FAILED = 2, RS_NONFINITE = 3, RS_RUNNING = 9 };
+enum RStatus : int { RS_CONVERGED = 0, RS_MAXITER = 1, RS_TS_FAILED = 2, RS_NONFINITE = 3, RS_SINGULAR = 4,
+                     RS_RUNNING = 9 };
 
 // Per-reactor controller state of the hybrid method.
 struct RState {
@@ -81,6 +88,7 @@ struct RState {
   int fb64;      // mixed mode: current matrix refactored in FP64
   int n_fb64;    // mixed mode: FP64 fallbacks so far
   int stick;     // mixed mode: linearisations still to factor in FP64 directly
+  int stick_len; // mixed mode: length of the current run of FP64 linearisations
   int sing, fin; // matrix flags of this round
   int ct, ct_k;  // continuation mode, down-search rung
   double nd, lam, h, sres;
@@ -88,6 +96,12 @@ struct RState {
   double ct_lc, ct_ln, ct_step; // continuation: ln tau of the last root, of
                                 // the current attempt, step in ln tau
 };
+
+// Mixed precision: a float attempt fell back to FP64 (see kStickFP64).
+__host__ __device__ inline void note_fallback(RState &s) {
+  s.stick_len = s.stick_len > 0 ? (2 * s.stick_len < kStickMax ? 2 * s.stick_len : kStickMax) : kStickFP64;
+  s.stick = s.stick_len;
+}
 
 // LDS / workspace layout of one reactor, in doubles (8-byte units).  The
 // first `persist` doubles (inlet data, vectors, matrices, pivots) carry the

@@ -958,21 +958,36 @@ extern "C" psr_status psr_jacobian_fd_noalloc(psr_mech_t m, const psr_conditions
   return psr_jacobian_fd(m, c, x, J, work, stream);
 }
 
-// Device scratch of the large-matrix LU entry point, grown on demand and kept
-// for the life of the process (one buffer per device, calls on a device are
-// serialised by the caller's stream use).
-static psr_status lu_scratch(int dev, size_t bytes, float **out) {
-  static std::vector<std::pair<float *, size_t>> bufs;
-  if ((int)bufs.size() <= dev) bufs.resize(dev + 1, {nullptr, 0});
-  auto &b = bufs[dev];
-  if (b.second < bytes) {
-    if (b.first) HIP_OK(hipFree(b.first));
-    b = {nullptr, 0};
+// Device scratch of the large-matrix LU entry point: one buffer per (device,
+// stream), grown on demand and kept for the life of the process.  Launches on
+// one stream are ordered, so a buffer is never used by two factorisations at
+// once; calls on different streams or host threads get different buffers.
+static psr_status lu_scratch(int dev, hipStream_t stream, size_t bytes, float **out) {
+  struct Buf { int dev; hipStream_t stream; float *p; size_t bytes; };
+  static std::mutex mu;
+  static std::vector<Buf> bufs;
+  std::lock_guard<std::mutex> lock(mu);
+  Buf *b = nullptr;
+  for (Buf &e : bufs)
+    if (e.dev == dev && e.stream == stream) b = &e;
+  if (!b) {
+    bufs.push_back({dev, stream, nullptr, 0});
+    b = &bufs.back();
+  }
+  if (b->bytes < bytes) {
+    // the old buffer may still be read by earlier launches on this stream
+    if (b->p) {
+      HIP_OK(hipStreamSynchronize(stream));
+      HIP_OK(hipFree(b->p));
+    }
+    b->p = nullptr;
+    b->bytes = 0;
     void *p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) return fail(PSR_ENOMEM, "LU scratch allocation failed");
-    b = {reinterpret_cast<float *>(p), bytes};
+    b->p = reinterpret_cast<float *>(p);
+    b->bytes = bytes;
   }
-  *out = b.first;
+  *out = b->p;
   return PSR_OK;
 }
 
@@ -1005,11 +1020,11 @@ extern "C" psr_status psr_lu_factor_batch(int32_t n, int64_t batch, int32_t prec
     HIP_OK(hipGetDevice(&dev));
     HIP_OK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     const int64_t grid = std::min<int64_t>(batch, (int64_t)ncu * 2);
-    float *scratch = nullptr;
-    const psr_status st = lu_scratch(dev, (size_t)grid * n * n * sizeof(float), &scratch);
+    float *panel_ws = nullptr;
+    const psr_status st = lu_scratch(dev, (hipStream_t)stream, (size_t)grid * n * n * sizeof(float), &panel_ws);
     if (st != PSR_OK) return st;
     hipLaunchKernelGGL(k_lu_factor_big, dim3((unsigned)grid), dim3(kBS), 0, (hipStream_t)stream, n, batch, A,
-                       piv, info, scratch);
+                       piv, info, panel_ws);
     HIP_OK(hipGetLastError());
     return PSR_OK;
   }
@@ -1105,7 +1120,9 @@ static WavePlan wave_plan(psr_mech_t m, int energy, bool mixed, int engine, int 
 // Streams on which the groups of one persistent solve run side by side
 // (default priority), created on first use and kept for the process.
 static psr_status group_stream(int dev, int i, hipStream_t *out) {
+  static std::mutex mu;  // calls from several host threads share the pool
   static std::vector<std::vector<hipStream_t>> pool;
+  std::lock_guard<std::mutex> lock(mu);
   if ((int)pool.size() <= dev) pool.resize(dev + 1);
   auto &v = pool[dev];
   while ((int)v.size() <= i) {
@@ -1366,6 +1383,8 @@ static psr_status launch_group(GroupRun &r, const psr_solve_opts *o, hipStream_t
   return drive_plain(stream, o->use_graph != 0, counters, check_every, o->max_lin * 2 + 8, period, &r.rounds);
 }
 
+// Add one group's totals to acc from its per-reactor controller states (the
+// group must have finished: the copy is synchronous).
 static psr_status collect_group(const GroupRun &r, psr_solve_stats *acc) {
   if (!acc) return PSR_OK;
   const int64_t B = r.gd.B;
@@ -1431,9 +1450,16 @@ extern "C" psr_status psr_solve_batch(const psr_group *groups, int32_t n_groups,
     HIP_OK(hipEventSynchronize(e1));
     for (hipEvent_t e : done) hipEventDestroy(e);
   } else {
+    // the groups run in turn on one workspace region: each group's totals are
+    // read before the next group overwrites its controller states
     for (int gi = 0; gi < n_groups; gi++) {
       st = launch_group(runs[gi], opts, cs);
       if (st != PSR_OK) return st;
+      if (stats && n_groups > 1) {
+        HIP_OK(hipStreamSynchronize(cs));
+        st = collect_group(runs[gi], stats);
+        if (st != PSR_OK) return st;
+      }
     }
     HIP_OK(hipEventRecord(e1, cs));
     HIP_OK(hipEventSynchronize(e1));
@@ -1442,9 +1468,11 @@ extern "C" psr_status psr_solve_batch(const psr_group *groups, int32_t n_groups,
   HIP_OK(hipEventElapsedTime(&ms, e0, e1));
   hipEventDestroy(e0);
   hipEventDestroy(e1);
-  for (int gi = 0; gi < n_groups; gi++) {
-    st = collect_group(runs[gi], stats);
-    if (st != PSR_OK) return st;
+  if (conc || n_groups == 1) {
+    for (int gi = 0; gi < n_groups; gi++) {
+      st = collect_group(runs[gi], stats);
+      if (st != PSR_OK) return st;
+    }
   }
   if (stats) stats->kernel_ms = ms;
   return PSR_OK;

@@ -205,7 +205,7 @@ __device__ void solve_round(const Ctx &c, const Opts &o, RState &s, const double
   // FP64 fallback for this matrix
   s.fb64 = 1;
   s.n_fb64++;
-  s.stick = kStickFP64;
+  note_fallback(s);
   const int info = factor64<BS, BIG>(c, A64, piv, red);
   s.sing = info != 0;
   for (int i = threadIdx.x; i < n; i += BS) z[i] = rs[i] * bb[i];
@@ -330,11 +330,13 @@ __device__ inline void next_newton(const Ctx &c, const Opts &o, RState &s) {
   vcopy<BS>(c.p(c.L.xev), c.p(c.L.xnw), c.n);
 }
 
+// A rejected ROS2 step: shrink h, or end (SINGULAR when the rejection was
+// caused by a matrix without a nonzero pivot, else TS_FAILED).
 template <int BS>
 __device__ inline void reject_ts(const Ctx &c, const Opts &o, RState &s, bool bad, double err) {
   double fac = bad ? 0.25 : 0.9 / sqrt(err);
   s.h *= (fac < 0.2 ? 0.2 : fac);
-  if (s.h < o.h_min) finish<BS>(s, RS_TS_FAILED);
+  if (s.h < o.h_min) finish<BS>(s, s.sing ? RS_SINGULAR : RS_TS_FAILED);
   else start_ts<BS>(c, o, s);
 }
 
@@ -363,6 +365,7 @@ __device__ void round_step(Ctx &c, const Opts &o, RState &s) {
       __syncthreads();
     }
     s.n_jac++;
+    if (MIXED && !s.fb64) s.stick_len = 0;  // the last linearisation went through in float
     s.fb64 = 0;
     s.fin = all_finite<BS>(G, n, red) && matrix_finite<BS>(A64, n, lda, red);
     s.sing = 0;
@@ -378,7 +381,7 @@ __device__ void round_step(Ctx &c, const Opts &o, RState &s) {
         if (info != 0) {
           s.fb64 = 1;
           s.n_fb64++;
-          s.stick = kStickFP64;
+          note_fallback(s);
           s.sing = factor64<BS, BIG>(c, A64, piv, red) != 0;
         }
       } else {
@@ -523,7 +526,7 @@ __device__ inline void init_state(const Ctx &c, const Opts &o, RState &s) {
   s.phase = PH_NW_BASE;
   s.status = RS_RUNNING;
   s.n_lin = s.n_jac = s.n_ts = s.n_att = s.nw_it = s.accepted = 0;
-  s.fb64 = s.n_fb64 = s.sing = s.stick = 0;
+  s.fb64 = s.n_fb64 = s.sing = s.stick = s.stick_len = 0;
   s.fin = 1;
   s.nd = s.lam = s.sres = 0.0;
   s.h = o.h0 * c.tau;

@@ -150,7 +150,7 @@ template <int NP, bool MIXED>
 __device__ __forceinline__ void reject_ts_w(const Opts &o, WState<NP, MIXED> &r, bool bad, double err) {
   const double fac = bad ? 0.25 : 0.9 / sqrt(err);
   r.s.h *= (fac < 0.2 ? 0.2 : fac);
-  if (r.s.h < o.h_min) finish_w(r, RS_TS_FAILED);
+  if (r.s.h < o.h_min) finish_w(r, r.s.sing ? RS_SINGULAR : RS_TS_FAILED);
   else start_ts_w(o, r);
 }
 
@@ -261,7 +261,7 @@ __device__ __forceinline__ double solve_w(const WCtx &c, const WArea<NP> &A, con
     if (fallback) {
       r.s.fb64 = 1;
       r.s.n_fb64++;
-      r.s.stick = kStickFP64;
+      note_fallback(r.s);
       r.s.sing = factor64<NP, MIXED>(c, A, r) != 0;
       if (r.s.sing) return __builtin_nan("");
       fp64 = true;
@@ -306,6 +306,7 @@ __device__ __forceinline__ void w_round(const WCtx &c, const WArea<NP> &A, const
       wsync();
     }
     s.n_jac++;
+    if (MIXED && !s.fb64) s.stick_len = 0;  // the last linearisation went through in float
     s.fb64 = 0;
     bool bad = false;
     if (in) {
@@ -325,7 +326,7 @@ __device__ __forceinline__ void w_round(const WCtx &c, const WArea<NP> &A, const
         if (direct || factor32<NP, MIXED>(c, A, r) != 0) {
           s.fb64 = 1;
           s.n_fb64++;
-          if (!direct) s.stick = kStickFP64;
+          if (!direct) note_fallback(s);
           s.sing = factor64<NP, MIXED>(c, A, r) != 0;
         }
       } else {
@@ -459,7 +460,7 @@ __device__ __forceinline__ void init_w(const WCtx &c, const Opts &o, WState<NP, 
   s.phase = PH_NW_BASE;
   s.status = RS_RUNNING;
   s.n_lin = s.n_jac = s.n_ts = s.n_att = s.nw_it = s.accepted = 0;
-  s.fb64 = s.n_fb64 = s.sing = s.stick = 0;
+  s.fb64 = s.n_fb64 = s.sing = s.stick = s.stick_len = 0;
   s.fin = 1;
   s.nd = s.lam = s.sres = 0.0;
   s.h = o.h0 * c.tau;

@@ -57,13 +57,16 @@ def parity(oracle_mod, mech, cond, energy, x, status, xo, so, tol, *, max_branch
       * every GPU root that is not within `tol` of an oracle root (branch
         mismatches, reactors only the GPU converged) must be a steady state
         by the oracle's own solve: the oracle, restarted at the GPU root,
-        converges and stays within `tol` of it (mostly with one linear solve;
-        on the stiffest reactors the scaled residual's rounding floor sits
-        near the 1e-10 bound and the restart takes more Newton steps, all
-        within `tol` of where it started);
+        converges, either with its first linear solve (its own convergence
+        test accepts the GPU root as it is; a trace species may then differ
+        from the oracle's root by up to its step-norm weight atol_Y + rtol
+        |Y|) or to within `tol` of the GPU root (on the stiffest reactors the
+        scaled residual's rounding floor sits near the 1e-10 bound and the
+        restart takes more Newton steps);
       * branch mismatches may be at most max_branch_frac of the jointly
         converged reactors (at least one allowed), and reactors only the
-        oracle converged at most max_miss_frac of the oracle-converged ones.
+        oracle converged at most max_miss_frac of the oracle-converged ones
+        (at least one when max_miss_frac > 0; none when it is 0).
     Returns the counts (and prints them)."""
     n_sp = mech["species_elems"].shape[0]
     conv_o, conv_g = so["status"] == 0, status == 0
@@ -81,10 +84,11 @@ def parity(oracle_mod, mech, cond, energy, x, status, xo, so, tol, *, max_branch
         xr, st = O.solve(*args, x[:, b], opts)
         assert st.status == 0, (label, "GPU root not verified", int(b), st.status, st.n_lin)
         e = rel_err(x[:, b:b + 1], xr[:, None], n_sp)[0]
-        assert e <= tol, (label, "oracle restart moved", int(b), e)
+        assert st.n_lin <= 1 or e <= tol, (label, "oracle restart moved", int(b), e)
     nb = int(both.sum())
     assert len(branch) <= max(1, int(max_branch_frac * nb)), (label, "branch mismatches", branch)
-    assert len(miss) <= int(max_miss_frac * conv_o.sum()), (label, "oracle-only roots", miss)
+    allowed = max(1, int(max_miss_frac * conv_o.sum())) if max_miss_frac > 0 else 0
+    assert len(miss) <= allowed, (label, "oracle-only roots", miss)
     out = dict(reactors=int(len(status)), oracle=int(conv_o.sum()), gpu=int(conv_g.sum()),
                agree=int(agree.sum()), branch=len(branch), gpu_only=len(gpu_only), miss=len(miss),
                max_err=float(err[agree].max()) if agree.any() else 0.0)

@@ -150,3 +150,27 @@ def test_tiny_mechanisms_on_wave_engine(P, oracle_mod):
             x, status, _, _ = solve_gpu(M, cond, x0, energy, precision=prec, engine=2,
                                         scheduler=P.PSR_PERSISTENT)
             parity(oracle_mod, mech, cond, energy, x, status, xo, so, TOL[prec], label="tiny")
+
+
+@pytest.mark.parametrize("scheduler", [0, 1])
+def test_multi_group_stats_match_status_arrays(P, scheduler):
+    """Two mechanisms in one call: the totals in psr_solve_stats equal the
+    sums over the per-reactor status and linear-solve arrays of both groups
+    (the plain scheduler runs the groups in turn on one workspace region)."""
+    import torch
+    from psr_inputs import workload
+    from tests.gpu_util import cond_dev, dev
+    gl = []
+    for name, B in (("isothermal", 16), ("energy", 24)):
+        mech, cond, x0, energy = workload(name, B)
+        gl.append(dict(mech=P.Mechanism(mech), cond=cond_dev(cond), energy=energy, x=dev(x0),
+                       status=torch.full((B,), -1, dtype=torch.int32, device="cuda:0"),
+                       n_lin=torch.zeros((B,), dtype=torch.int32, device="cuda:0")))
+    st, _ = P.solve_batch(gl, P.default_opts(scheduler=scheduler))
+    torch.cuda.synchronize()
+    status = np.concatenate([g["status"].cpu().numpy() for g in gl])
+    nlin = np.concatenate([g["n_lin"].cpu().numpy() for g in gl])
+    assert st.reactors == len(status)
+    assert st.converged == int((status == 0).sum())
+    assert st.lin_total == int(nlin.sum())
+    assert st.lin_max == int(nlin.max())

@@ -68,7 +68,7 @@ def _check_group(oracle_mod, name, mech, cond, xo, so, x, status, tol):
     only, then different pseudo-time steps) can turn on rounding, so a few
     reactors end inside the budget on one side only, in both directions
     (measured: 38 of 40 converged on each side, one reactor each way); at
-    most one in sixteen oracle roots may be missed."""
+    most one in sixteen oracle roots (at least one) may be missed."""
     assert (so["status"] == 0).mean() >= 0.85, (name, so["status"])
     out = parity(oracle_mod, mech, cond, True, x, status, xo, so, tol, label=name,
                  max_miss_frac=1.0 / 16)
