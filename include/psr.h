@@ -46,7 +46,9 @@ enum {
   PSR_R_CONVERGED = 0, /* root found: weighted Newton step <= 1 and scaled residual <= ftol */
   PSR_R_MAXITER = 1,   /* linear-solve budget spent                                         */
   PSR_R_TS_FAILED = 2, /* pseudo-transient step size fell below h_min                        */
-  PSR_R_NONFINITE = 3, /* converged iterate not finite                                       */
+  PSR_R_NONFINITE = 3, /* converged iterate not finite, or inputs outside the domain: P, tau or
+                          T_in not positive and finite, or Y_in or the initial x not finite (x
+                          is then left as given and no work is done for the reactor)          */
   PSR_R_SINGULAR = 4   /* pseudo-transient step size fell below h_min after a step rejected
                           because its matrix had no nonzero pivot                          */
 };

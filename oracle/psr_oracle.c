@@ -733,6 +733,14 @@ int om_solve(const om_mech *m, const om_cond *c, const om_opts *o, double *x, om
 {
   const int N = m->n_sp, n = om_n_unknowns(m, c->energy);
   memset(st, 0, sizeof(*st));
+  /* Eqs. 1-3 need a positive, finite pressure, residence time and inlet
+   * temperature, and finite inlet and initial data; a reactor outside that
+   * domain is reported as non-finite at once and its x is left as given.  */
+  int bad = !(c->P > 0.0 && c->P < HUGE_VAL) || !(c->tau > 0.0 && c->tau < HUGE_VAL) ||
+            !(c->T_in > 0.0 && c->T_in < HUGE_VAL);
+  for (int i = 0; i < N; i++) bad |= !isfinite(c->Y_in[i]);
+  for (int i = 0; i < n; i++) bad |= !isfinite(x[i]);
+  if (bad) { st->status = OM_NONFINITE; return st->status; }
   for (int i = 0; i < N; i++) if (x[i] < 0.0) x[i] = 0.0;
   double h = o->h0 * c->tau;
   int attempt = 1, accepted = 0, first = 1;

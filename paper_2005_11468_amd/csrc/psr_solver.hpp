@@ -535,6 +535,16 @@ __device__ inline void init_state(const Ctx &c, const Opts &o, RState &s) {
   s.tau_c = c.tau;
   s.ct_lc = s.ct_ln = s.ct_step = 0.0;
   double *x = c.p(c.L.x);
+  // inputs outside the domain of Eqs. 1-3: reported at once, x left as given
+  const double *Yin = c.p(c.L.Yin);
+  int bad = 0;
+  for (int i = threadIdx.x; i < c.n; i += BS) bad |= !isfinite(x[i]) || (i < c.N && !isfinite(Yin[i]));
+  bad = block_or<BS>(bad, c.p(c.L.red));
+  if (bad || !(c.P > 0.0 && c.P < __builtin_inf()) || !(c.tau > 0.0 && c.tau < __builtin_inf()) ||
+      !(c.Tin > 0.0 && c.Tin < __builtin_inf())) {
+    finish<BS>(s, RS_NONFINITE);
+    return;
+  }
   for (int i = threadIdx.x; i < c.N; i += BS) x[i] = x[i] > 0.0 ? x[i] : 0.0;
   __syncthreads();
   start_attempt<BS>(c, o, s);

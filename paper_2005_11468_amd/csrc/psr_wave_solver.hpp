@@ -468,6 +468,14 @@ __device__ __forceinline__ void init_w(const WCtx &c, const Opts &o, WState<NP, 
   s.ct_k = 0;
   s.tau_c = c.tau;
   s.ct_lc = s.ct_ln = s.ct_step = 0.0;
+  // inputs outside the domain of Eqs. 1-3: reported at once, x left as given
+  const bool bad_lane = (lane < c.N && !isfinite(c.Yin)) || (lane < c.n && !isfinite(x0));
+  if (!(c.P > 0.0 && c.P < __builtin_inf()) || !(c.tau > 0.0 && c.tau < __builtin_inf()) ||
+      !(c.Tin > 0.0 && c.Tin < __builtin_inf()) || wany(bad_lane)) {
+    r.x = lane < c.n ? x0 : 0.0;
+    finish_w(r, RS_NONFINITE);
+    return;
+  }
   start_attempt_w(o, r, c.tau);
 }
 
