@@ -104,6 +104,7 @@ def lib():
         L.om_soot_fxy.argtypes = [dp, C.c_int, C.c_int]
         L.om_soot_fxy.restype = C.c_double
         L.om_soot_sources.argtypes = [mp, C.c_double, C.c_double, C.c_double, dp, dp, dp, dp, dp]
+        L.om_soot_outputs.argtypes = [mp, dp, dp]
         L.om_lu_factor.argtypes = [C.c_int, dp, ip]
         L.om_lu_factor.restype = C.c_int
         L.om_lu_solve.argtypes = [C.c_int, dp, ip, dp]
@@ -174,6 +175,20 @@ class Mechanism:
         return self.n_sp + (1 if energy else 0) + (6 if energy and self.soot is not None else 0)
 
     # -- soot moments (MOMIC) -------------------------------------------------
+    def soot_outputs(self, x):
+        """(f_v, N, d) per reactor of states x [n][B] (or one state [n]) of a
+        sooting mechanism with a T unknown: volume fraction, number density
+        (cm^-3) and mean-volume sphere diameter (cm)."""
+        x = np.asarray(x, dtype=np.float64)
+        X = x.reshape(x.shape[0], -1)
+        out = np.zeros((3, X.shape[1]))
+        for b in range(X.shape[1]):
+            lnM = np.ascontiguousarray(X[self.n_sp + 1:self.n_sp + 7, b])
+            o = np.zeros(3)
+            lib().om_soot_outputs(C.byref(self.s), _dp(lnM), _dp(o))
+            out[:, b] = o
+        return out if x.ndim == 2 else out[:, 0]
+
     def soot_sources(self, T, CP, CG, lnM):
         """(R, W, G, sinks): nucleation, growth and coagulation sources of the
         six moments, and the precursor / growth-species sinks (mol/cm^3/s)."""
@@ -185,7 +200,7 @@ class Mechanism:
 
     def _cond(self, P, tau, T_in, Y_in, energy):
         Y_in = np.ascontiguousarray(Y_in, dtype=np.float64)
-        return _Cond(float(P), float(tau), float(T_in), _dp(Y_in), int(bool(energy))), Y_in
+        return _Cond(float(P), float(tau), float(T_in), _dp(Y_in), int(energy)), Y_in
 
     def residual(self, P, tau, T_in, Y_in, energy, x):
         c, keep = self._cond(P, tau, T_in, Y_in, energy)

@@ -191,7 +191,11 @@ double om_scaled_residual(const om_mech *m, const om_cond *c, const double *x)
     if (den > 0.0 && fabs(F[i]) / den > worst) worst = fabs(F[i]) / den;
     if (!(den >= 0.0) || F[i] != F[i]) worst = INFINITY;
   }
-  if (c->energy) {
+  if (c->energy == 2) {
+    double den = OM_V * (fabs(T) + fabs(c->T_in)) / c->tau;
+    if (fabs(F[N]) / den > worst) worst = fabs(F[N]) / den;
+    if (F[N] != F[N]) worst = INFINITY;
+  } else if (c->energy) {
     thermo_r(m, c->T_in, NULL, hin, NULL);
     double den = 0.0;
     for (int i = 0; i < N; i++) {
@@ -299,7 +303,9 @@ void om_jacobian(const om_mech *m, const om_cond *c, const double *x, double *J)
     if (c->energy)
       J[(size_t)i * n + N] = -mdot / T * (x[i] - c->Y_in[i]) - OM_V * m->W[i] * dwdT[i];
   }
-  if (c->energy) {
+  if (c->energy == 2) {
+    J[(size_t)N * n + N] = OM_V / c->tau;
+  } else if (c->energy) {
     thermo_r(m, c->T_in, NULL, hin, NULL);
     double Qin = 0.0, dQin = 0.0;
     for (int i = 0; i < N; i++) {
@@ -350,7 +356,8 @@ void om_jacobian_complex_step(const om_mech *m, const om_cond *c, const double *
 }
 
 /* Diagonal mass matrix of the transient form of Eqs. 2-3:
- * rho V for each species row, rho V cp_mix for the energy row, V M_r for
+ * rho V for each species row, rho V cp_mix for the energy row (V for the
+ * prescribed-temperature row, which relaxes T to T_in over tau), V M_r for
  * the ln M_r rows (d M_r/dt = M_r d ln M_r/dt).                             */
 void om_mass_diag(const om_mech *m, const om_cond *c, const double *x, double *M)
 {
@@ -365,11 +372,26 @@ void om_mass_diag(const om_mech *m, const om_cond *c, const double *x, double *M
     thermo_r(m, T, cp, NULL, NULL);
     double cpmix = 0.0;
     for (int i = 0; i < N; i++) cpmix += x[i] * OM_R * cp[i] / m->W[i];
-    M[N] = rho * OM_V * cpmix;
+    M[N] = c->energy == 2 ? OM_V : rho * OM_V * cpmix;
     free(cp);
     if (m->soot)
       for (int r = 0; r < 6; r++) M[N + 1 + r] = OM_V * exp(x[N + 1 + r]);
   }
+}
+
+/* Soot outputs of one reactor from its moments (the quantities of the
+ * Section 5 sweeps, Figs. 1-2): number density N = M_0 (cm^-3), volume
+ * fraction f_v = M_1 m_C / rho_s (M_1 carbon atoms per cm^3 at mass m_C
+ * each, soot density rho_s) and the diameter of a sphere of the mean
+ * particle volume, d = (6 f_v / (pi N))^(1/3) (cm).  out = (f_v, N, d).   */
+void om_soot_outputs(const om_mech *m, const double *lnM, double *out)
+{
+  const om_soot *sd = m->soot;
+  const double mC = m->elem_w[sd->carbon] / OM_NA;
+  const double N0 = exp(lnM[0]), fv = exp(lnM[1]) * mC / sd->soot_density;
+  out[0] = fv;
+  out[1] = N0;
+  out[2] = cbrt(6.0 * fv / (OM_PI * N0));
 }
 
 /* Textbook LU with partial pivoting (Golub & Van Loan, Alg. 3.4.1), row

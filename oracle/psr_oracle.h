@@ -66,7 +66,8 @@ typedef struct {
   double tau;        /* residence time, s                   */
   double T_in;       /* inlet temperature (isothermal: T)   */
   const double *Y_in;/* [N] inlet mass fractions            */
-  int energy;        /* 0: isothermal, unknowns Y; 1: (Y, T) */
+  int energy;        /* 0: isothermal, unknowns Y; 1: (Y, T) with the energy
+                        balance; 2: (Y, T) with T prescribed (T = T_in)    */
 } om_cond;
 
 typedef struct {
@@ -117,6 +118,8 @@ double om_scaled_residual(const om_mech *m, const om_cond *c, const double *x);
 void om_jacobian(const om_mech *m, const om_cond *c, const double *x, double *J);
 void om_jacobian_complex_step(const om_mech *m, const om_cond *c, const double *x, double *J);
 void om_mass_diag(const om_mech *m, const om_cond *c, const double *x, double *M);
+/* (f_v, N, d) of a sooting reactor from its ln M_0..ln M_5 */
+void om_soot_outputs(const om_mech *m, const double *lnM, double *out);
 
 /* MOMIC pieces, exported for the tests.  lnM: [6] ln M_r.               */
 double om_soot_ln_mu(const double *lnM, double p);

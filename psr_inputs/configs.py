@@ -35,6 +35,9 @@ MECH_SPECS = {
     "uneven_b": (100, 600, 49),
     "uneven_c": (200, 1200, 43),
     "soot": (150, 900, 56),
+    # the same species and reactions with stronger soot kinetics (below), for
+    # the sooting sweeps at a prescribed temperature
+    "soot_sweep": (150, 900, 56),
     # stand-in for the 101-species / 542-reaction mechanism of the paper's
     # single-Newton-iteration speed-up measurement (Section 6)
     "newton101": (101, 542, 71),
@@ -48,6 +51,12 @@ MECH_SPECS = {
 SOOT_CONSTANTS = dict(carbon=0, A_nuc=1.0e9, beta_nuc=0.0, E_nuc=5.0e4,
                       A_grow=1.0e9, beta_grow=0.0, E_grow=4.0e4,
                       site_density=2.3e15, soot_density=1.8, coag_scale=1.0)
+
+# Soot constants of the sooting sweeps: nucleation 1e4 and growth 1e3 times
+# faster, which puts the steady soot of the 1500-2000 K, 5-95 ms sweeps at
+# f_v 0.5-10 ppm and d 30-200 nm (the range of the paper's Figs. 1-2); at the
+# constants above these set-temperature reactors hold f_v ~ 1e-7 ppm.
+SOOT_SWEEP_CONSTANTS = dict(SOOT_CONSTANTS, A_nuc=1.0e13, A_grow=1.0e12)
 
 # The uneven-batching workload: three mechanisms in one solve, 65536 reactors
 # split 50 / 35 / 15 %, tau log-uniform in [1e-6, 1] s, phi inlet; one
@@ -80,10 +89,11 @@ WORKLOADS = {
 @lru_cache(maxsize=None)
 def mechanism(name: str) -> dict:
     n_sp, n_rx, seed, *rest = MECH_SPECS[name]
-    soot = name == "soot"
+    soot = name in ("soot", "soot_sweep")
     mech = make_mechanism(n_sp, n_rx, seed, heat_scale=rest[0] if rest else 1.0, soot=soot)
     if soot:
-        mech["soot"] = dict(precursor=mech["precursor"], growth=mech["growth"], **SOOT_CONSTANTS)
+        consts = SOOT_SWEEP_CONSTANTS if name == "soot_sweep" else SOOT_CONSTANTS
+        mech["soot"] = dict(precursor=mech["precursor"], growth=mech["growth"], **consts)
     return mech
 
 
@@ -157,3 +167,29 @@ def sweep_workload(param: str, n_chains: int, seed: int = 82, mech_name: str = "
     values = np.ascontiguousarray(np.repeat(steps[:, None], B, axis=1))
     cond[param] = values[0].copy()
     return mech, cond, initial_guess(cond, False), values
+
+
+# The sooting reactors of the Section 5 sweeps: the 150/900 soot mechanism
+# (with the sweep soot constants) at a prescribed reactor temperature (energy mode 2: T stays an unknown pinned
+# to T_in), fuel-rich inlet; chain 0 has the paper's equivalence ratio 2.5,
+# the others draw it from U[2, 3] so a batch holds distinct chains.  The
+# moments start from 1e3 nuclei per cm^3 and T from the first step's value.
+FIXED_T = 2
+
+
+def soot_sweep_workload(param: str, n_chains: int, seed: int = 84):
+    """(mechanism, conditions, x0, values [n_steps][B]) of a sooting
+    continuation sweep over `param` ("T_in" or "tau")."""
+    spec = SWEEPS[param]
+    mech = mechanism("soot_sweep")
+    B = int(n_chains)
+    cond = make_conditions(mech, B, seed, recipe="phi", phi_range=(2.0, 3.0))
+    ref = make_conditions(mech, 1, seed, recipe="phi", phi_range=(2.5, 2.5))
+    cond["Y_in"][:, 0] = ref["Y_in"][:, 0]
+    other, val = spec["fixed"]
+    cond[other] = np.full(B, float(val))
+    steps = np.asarray(spec["values"], dtype=np.float64)
+    values = np.ascontiguousarray(np.repeat(steps[:, None], B, axis=1))
+    cond[param] = values[0].copy()
+    x0 = initial_guess(cond, True, T0=float(cond["T_in"][0]), soot_nucleus=soot_nucleus_size(mech))
+    return mech, cond, x0, values

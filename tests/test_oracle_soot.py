@@ -188,3 +188,28 @@ def test_monodisperse_sources_absolute(oracle_mod, soot_mech):
     assert G[0] == pytest.approx(-4.78800208182457e9, rel=1e-11)
     assert W[1] == pytest.approx(3.052713816068612e11, rel=1e-11)
     assert R[0] == pytest.approx(1.5765598674782403e14, rel=1e-11)
+
+
+def test_soot_outputs_of_a_monodisperse_population(oracle_mod):
+    """N spheres per cm^3 of diameter d: volume fraction N pi d^3 / 6 (a
+    geometric identity, independent of the moment formulas), number density
+    N and diameter d back; doubling N at fixed particle size doubles f_v and
+    keeps d."""
+    from psr_inputs import configs
+    mech = configs.mechanism("soot")
+    M = oracle_mod.Mechanism(mech)
+    sd = mech["soot"]
+    mC = mech["elem_weight"][sd["carbon"]] / 6.02214076e23
+    for d_nm, N in ((10.0, 1e10), (1.0, 3e12), (80.0, 2e8)):
+        d = d_nm * 1e-7
+        m = sd["soot_density"] * np.pi * d ** 3 / 6.0 / mC  # carbon atoms per particle
+        lnM = np.log(N) + np.arange(6) * np.log(m)
+        x = np.concatenate([np.zeros(M.n_sp + 1), lnM])
+        fv, n_out, d_out = M.soot_outputs(x)
+        assert fv == pytest.approx(N * np.pi * d ** 3 / 6.0, rel=1e-12)
+        assert n_out == pytest.approx(N, rel=1e-14)
+        assert d_out == pytest.approx(d, rel=1e-12)
+        x2 = x.copy()
+        x2[M.n_sp + 1:] += np.log(2.0)
+        fv2, n2, d2 = M.soot_outputs(x2)
+        assert fv2 == pytest.approx(2 * fv, rel=1e-13) and d2 == pytest.approx(d, rel=1e-13)
