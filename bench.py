@@ -478,6 +478,43 @@ def continuation(P, chains=4096):
     return out
 
 
+def soot_sweeps(P, chains=256):
+    """The Section 5 sweeps on sooting reactors at a prescribed temperature
+    (energy mode 2; 150/900 soot mechanism, chain 0 at equivalence ratio
+    2.5): temperature 1500 -> 2000 K at 5 ms and residence time 5 -> 95 ms at
+    1750 K, mixed-precision persistent psr_sweep_batch, then psr_soot_outputs
+    along each path; reports throughput and chain 0's soot volume fraction
+    (ppm), number density (cm^-3) and diameter (nm) per step (Figs. 1-2)."""
+    import torch
+    from psr_inputs.configs import FIXED_T, soot_sweep_workload
+    from tests.gpu_util import cond_dev, dev
+    out = {"chains": chains}
+    o = P.default_opts(precision=P.PSR_MIXED, scheduler=P.PSR_PERSISTENT)
+    for param in ("T_in", "tau"):
+        mech, cond, x0, values = soot_sweep_workload(param, chains)
+        M = P.Mechanism(mech)
+        x0d, vd = dev(x0), dev(values)
+        g = dict(mech=M, cond=cond_dev(cond), energy=FIXED_T, x=x0d.clone(),
+                 status=torch.empty(chains, dtype=torch.int32, device="cuda:0"))
+        _, xp, sp, ws = P.sweep_batch(g, param, vd, o)  # warm-up (same inputs)
+        g["x"].copy_(x0d)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, xp, sp, _ = P.sweep_batch(g, param, vd, o, workspace=ws, x_path=xp, status_path=sp)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        soot0 = torch.stack([P.soot_outputs(M, xp[k])[:, 0] for k in range(values.shape[0])]).cpu().numpy()
+        out[param] = {"steps": int(values.shape[0]), "converged": int(st.converged),
+                      "reactor_solves": int(st.reactors), "wall_ms": wall * 1e3,
+                      "converged_per_s": st.converged / wall,
+                      "chain0": {"values": values[:, 0].tolist(), "status": sp[:, 0].cpu().numpy().tolist(),
+                                 "f_v_ppm": (soot0[:, 0] * 1e6).tolist(), "N_per_cm3": soot0[:, 1].tolist(),
+                                 "d_nm": (soot0[:, 2] * 1e7).tolist()}}
+        print(f"soot sweep {param}: {st.converged}/{st.reactors} converged in {wall * 1e3:.1f} ms",
+              file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -492,6 +529,8 @@ def main():
                     help="oracle parity sample per group of the 65536-reactor workload (-1: skip the leg)")
     ap.add_argument("--soot-sample", type=int, default=32,
                     help="oracle parity sample of the 8192-reactor sooting workload (-1: skip the leg)")
+    ap.add_argument("--soot-sweep-chains", type=int, default=256,
+                    help="chains of the sooting sweeps at a prescribed temperature (0: skip)")
     ap.add_argument("--sweep-chains", type=int, default=4096,
                     help="chains of the continuation sweeps (0: skip)")
     ap.add_argument("--newton-sizes", default="100,1000,10000,100000,1000000",
@@ -601,6 +640,7 @@ def main():
     sizes = [int(v) for v in args.newton_sizes.split(",") if v.strip() and int(v) > 0]
     newton = newton_sweep(P, sizes) if sizes else None
     sweep_leg = continuation(P, args.sweep_chains) if args.sweep_chains > 0 else None
+    soot_sweep_leg = soot_sweeps(P, args.soot_sweep_chains) if args.soot_sweep_chains > 0 else None
 
     # roofline of the dominant kernel (the persistent solve kernel): the
     # solver's own counts of linearisations and rounds times the algorithmic
@@ -648,6 +688,7 @@ def main():
         "soot": soot_leg,
         "newton101": newton,
         "continuation": sweep_leg,
+        "soot_sweeps": soot_sweep_leg,
         "parity": parity,
         "cpu_baseline": cpu,
     }

@@ -62,7 +62,8 @@ typedef struct psr_mech *psr_mech_t; /* opaque; immutable after creation */
  * Sections 1-2 and 6, modelled with Frenklach's method of moments with
  * interpolative closure, MOMIC).  Six extra unknowns per reactor, ln M_r for
  * r = 0..5, where M_r = sum_i m_i^r N_i per cm^3 with particle mass m in
- * carbon atoms; only with the energy equation.  Source terms:
+ * carbon atoms; only for reactors with a temperature unknown (energy 1 or
+ * 2).  Source terms:
  *   nucleation   I = k_n [P]^2 (mol/cm^3/s) from two molecules of the
  *                pure-carbon precursor P; nucleus of C = 2 n_C(P) atoms;
  *                R_r = N_A I C^r; P consumed at 2 I
@@ -117,16 +118,22 @@ typedef struct {
 psr_status psr_create_mechanism(const psr_mech_desc *desc, psr_mech_t *out);
 psr_status psr_destroy_mechanism(psr_mech_t mech);
 
-/* Number of unknowns per reactor: N (isothermal), N + 1 (energy) or
- * N + 7 (energy with soot: Y, T, ln M_0..ln M_5).  Soot mechanisms require
- * energy reactors (the residual, Jacobian and solve calls return
- * PSR_EINVAL otherwise). */
+/* Number of unknowns per reactor: N (isothermal), N + 1 (energy 1 or 2) or
+ * N + 7 (energy 1 or 2 with soot: Y, T, ln M_0..ln M_5).  Soot mechanisms
+ * require a temperature unknown (the residual, Jacobian and solve calls
+ * return PSR_EINVAL otherwise). */
 int32_t psr_num_unknowns(psr_mech_t mech, int32_t energy);
 
 /* Reactor conditions: device pointers, [B] or [N][B]. */
 typedef struct {
   int64_t n_reactors;  /* B >= 1                                               */
-  int32_t energy;      /* 0: isothermal at T = T_in, unknowns Y; 1: unknowns (Y, T) */
+  int32_t energy;      /* 0: isothermal at T = T_in, unknowns Y;
+                          1: unknowns (Y, T), energy balance (Eq. 3);
+                          2: unknowns (Y, T), reactor temperature prescribed: T = T_in
+                             through the row F_T = V (T - T_in) / tau (the set-temperature
+                             sooting reactors of the Section 5 sweeps; the root is the
+                             isothermal root with T = T_in).  Mode 2 runs on the
+                             workgroup engine. */
   const double *P;     /* [B] pressure, Pa                                     */
   const double *tau;   /* [B] residence time, s                                */
   const double *T_in;  /* [B] inlet temperature (isothermal: reactor T), K     */
@@ -157,6 +164,16 @@ psr_status psr_jacobian(psr_mech_t mech, const psr_conditions *cond, const doubl
  * `stream`; errors as psr_residual, PSR_EINVAL for a null x, J or work. */
 psr_status psr_jacobian_fd(psr_mech_t mech, const psr_conditions *cond, const double *x, double *J,
                            double *work, void *stream);
+
+/* Soot outputs of a batch of sooting reactors (the quantities of the Section 5
+ * sweeps, Figs. 1-2), from the moments of states x (device [n][B], n = N + 7):
+ *   out[0][b] = f_v = M_1 m_C / rho_s       soot volume fraction
+ *   out[1][b] = N   = M_0                   particle number density, cm^-3
+ *   out[2][b] = d   = (6 f_v / (pi N))^(1/3) diameter of a sphere of the
+ *                                            mean particle volume, cm
+ * out: device [3][B], written by the call.  Asynchronous on `stream`.
+ * Errors: PSR_EINVAL (null pointer, B < 1, mechanism without soot). */
+psr_status psr_soot_outputs(psr_mech_t mech, int64_t n_reactors, const double *x, double *out, void *stream);
 
 /* psr_jacobian_fd for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):

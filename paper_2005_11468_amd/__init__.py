@@ -70,8 +70,8 @@ class Mechanism:
         self.handle = h
         self._L = L  # keeps the library reachable for __del__ at interpreter exit
 
-    def n_unknowns(self, energy: bool) -> int:
-        return int(_lib.load().psr_num_unknowns(self.handle, 1 if energy else 0))
+    def n_unknowns(self, energy) -> int:
+        return int(_lib.load().psr_num_unknowns(self.handle, _energy(energy)))
 
     def __del__(self):
         h, lib = getattr(self, "handle", None), getattr(self, "_L", None)
@@ -88,7 +88,16 @@ def _check_state(mech: Mechanism, energy: bool, x, B: int, name: str = "x"):
         raise ValueError(f"{name} must have shape ({n}, {B}), got {tuple(x.shape)}")
 
 
-def _conditions(cond: dict, energy: bool):
+def _energy(energy) -> int:
+    """Energy mode of psr_conditions: False/0 isothermal, True/1 energy
+    balance, 2 prescribed reactor temperature."""
+    e = int(energy)
+    if e not in (0, 1, 2):
+        raise ValueError("energy must be 0, 1 or 2")
+    return e
+
+
+def _conditions(cond: dict, energy):
     P = _dev_f64(cond["P"], "P")
     tau = _dev_f64(cond["tau"], "tau")
     Tin = _dev_f64(cond["T_in"], "T_in")
@@ -96,7 +105,7 @@ def _conditions(cond: dict, energy: bool):
     B = P.shape[0]
     if tau.shape[0] != B or Tin.shape[0] != B or Yin.shape[1] != B:
         raise ValueError("condition arrays disagree on the batch size")
-    return _lib.Conditions(B, 1 if energy else 0, _ptr(P), _ptr(tau), _ptr(Tin), _ptr(Yin))
+    return _lib.Conditions(B, _energy(energy), _ptr(P), _ptr(tau), _ptr(Tin), _ptr(Yin))
 
 
 def residual(mech: Mechanism, cond: dict, energy: bool, x, F=None, scaled=None, stream=None):
@@ -126,6 +135,21 @@ def jacobian(mech: Mechanism, cond: dict, energy: bool, x, J=None, stream=None):
     _lib.check(_lib.load().psr_jacobian(mech.handle, C.byref(c), _ptr(x), _ptr(J), _stream(stream)),
                "psr_jacobian")
     return J
+
+
+def soot_outputs(mech: Mechanism, x, out=None, stream=None):
+    """psr_soot_outputs: (f_v, N [cm^-3], d [cm]) per reactor of sooting
+    states x ([N + 7][B] float64 device tensor) -> [3][B]."""
+    torch = _torch()
+    x = _dev_f64(x, "x")
+    n, B = x.shape
+    if n != mech.n_species + 7:
+        raise ValueError(f"x must have {mech.n_species + 7} rows (Y, T, ln M_0..ln M_5)")
+    if out is None:
+        out = torch.empty((3, B), dtype=torch.float64, device=x.device)
+    _lib.check(_lib.load().psr_soot_outputs(mech.handle, B, _ptr(x), _ptr(out), _stream(stream)),
+               "psr_soot_outputs")
+    return out
 
 
 def jacobian_fd(mech: Mechanism, cond: dict, energy: bool, x, J=None, work=None, stream=None):

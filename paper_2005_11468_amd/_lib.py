@@ -77,6 +77,7 @@ SYMBOLS = {
     "psr_jacobian": ([vp, C.POINTER(Conditions), vp, vp, vp], C.c_int),
     "psr_jacobian_fd": ([vp, C.POINTER(Conditions), vp, vp, vp, vp], C.c_int),
     "psr_jacobian_fd_noalloc": ([vp, C.POINTER(Conditions), vp, vp, vp], C.c_int),
+    "psr_soot_outputs": ([vp, C.c_int64, vp, vp, vp], C.c_int),
     "psr_lu_factor_batch": ([C.c_int32, C.c_int64, C.c_int32, vp, vp, vp, vp], C.c_int),
     "psr_lu_solve_batch": ([C.c_int32, C.c_int64, vp, vp, vp, vp], C.c_int),
     "psr_default_opts": ([C.POINTER(SolveOpts)], None),

@@ -435,7 +435,7 @@ __device__ double residual(Ctx &c, const double *x, double *F, bool want_sres) {
     const double sk = sink(i);
     const double Fi = mdot * (x[i] - Yin[i]) - kV * m.W[i] * (w - sk);
     F[i] = Fi;
-    if (c.energy) {
+    if (c.energy == 1) {
       const double H = kR * T * hRT[i];
       inflow += Yin[i] * (H - Hin[i]) / m.W[i];
       chem += H * (w - sk);
@@ -448,7 +448,15 @@ __device__ double residual(Ctx &c, const double *x, double *F, bool want_sres) {
     }
   }
   double FT = 0.0;
-  if (c.energy) {
+  if (c.energy == 2) {  // prescribed reactor temperature: T pinned to T_in
+    FT = kV * (T - c.Tin) / c.tau;
+    if (tid == 0) F[N] = FT;
+    if (want_sres && tid == 0) {
+      double r = fabs(FT) / (kV * (fabs(T) + fabs(c.Tin)) / c.tau);
+      if (FT != FT) r = __builtin_inf();
+      sr = fmax(sr, r);
+    }
+  } else if (c.energy) {
     const double in_s = block_sum<BS>(inflow, red);
     const double ch_s = block_sum<BS>(chem, red);
     FT = mdot * in_s + kV * ch_s;
@@ -456,7 +464,7 @@ __device__ double residual(Ctx &c, const double *x, double *F, bool want_sres) {
   }
   double sres = 0.0;
   if (want_sres) {
-    if (c.energy) {
+    if (c.energy == 1) {
       double den = 0.0;
       for (int i = tid; i < N; i += BS) {
         const double H = kR * T * hRT[i];
@@ -490,7 +498,8 @@ __device__ double residual(Ctx &c, const double *x, double *F, bool want_sres) {
 }
 
 // Mass-matrix diagonal of the transient form: rho V (species), rho V cp_mix
-// (energy).  Uses the state of the last residual() call at the same x.
+// (energy; V for a prescribed temperature, relaxed to T_in over tau).  Uses
+// the state of the last residual() call at the same x.
 template <int BS>
 __device__ void mass_diag(Ctx &c, const double *x, double *M) {
   const int N = c.N, tid = threadIdx.x;
@@ -501,7 +510,7 @@ __device__ void mass_diag(Ctx &c, const double *x, double *M) {
     for (int i = tid; i < N; i += BS) cp += x[i] * kR * cpR[i] / c.m.W[i];
   const double cpmix = c.energy ? block_sum<BS>(cp, red) : 0.0;
   for (int i = tid; i < N; i += BS) M[i] = c.rho * kV;
-  if (c.energy && tid == 0) M[N] = c.rho * kV * cpmix;
+  if (c.energy && tid == 0) M[N] = c.energy == 2 ? kV : c.rho * kV * cpmix;
   // soot: d M_r/dt = M_r d ln M_r/dt
   if (c.energy && c.m.soot && tid < 6) M[N + 1 + tid] = kV * exp(x[N + 1 + tid]);
   __syncthreads();
@@ -529,7 +538,7 @@ __device__ void soot_jacobian(Ctx &c, const double *x, double *A, int lda) {
     const double dsP = sk[1] * dCP, dsG = w1[7] * dCG * gD;
     A[(int64_t)P * lda + mm] += kV * m.W[P] * dsP;
     A[(int64_t)Gs * lda + mm] += kV * m.W[Gs] * dsG;
-    A[(int64_t)N * lda + mm] -= kV * (HP * dsP + HG * dsG);
+    if (c.energy == 1) A[(int64_t)N * lda + mm] -= kV * (HP * dsP + HG * dsG);
     for (int r = 0; r < 6; r++) {
       const double *o = w + soot::OUT + 12 * r;
       A[(int64_t)(N + 1 + r) * lda + mm] -= kV * (o[9] * dCP + o[10] * dCG);
@@ -542,7 +551,8 @@ __device__ void soot_jacobian(Ctx &c, const double *x, double *A, int lda) {
       const double dsP = sk[2] + sk[1] * dCP, dsG = (w1[8] + w1[7] * dCG) * gD;
       A[(int64_t)P * lda + N] += kV * m.W[P] * dsP;
       A[(int64_t)Gs * lda + N] += kV * m.W[Gs] * dsG;
-      A[(int64_t)N * lda + N] -= kV * (kR * cpR[P] * sk[0] + HP * dsP + kR * cpR[Gs] * w1[0] * gD + HG * dsG);
+      if (c.energy == 1)
+        A[(int64_t)N * lda + N] -= kV * (kR * cpR[P] * sk[0] + HP * dsP + kR * cpR[Gs] * w1[0] * gD + HG * dsG);
       for (int r = 0; r < 6; r++) {
         const double *o = w + soot::OUT + 12 * r;
         A[(int64_t)(N + 1 + r) * lda + N] -= kV * (o[11] + o[9] * dCP + o[10] * dCG);
@@ -550,7 +560,7 @@ __device__ void soot_jacobian(Ctx &c, const double *x, double *A, int lda) {
     } else {
       const int j = col - N - 1;
       A[(int64_t)Gs * lda + col] += kV * m.W[Gs] * w1[1 + j] * gD;
-      A[(int64_t)N * lda + col] -= kV * HG * w1[1 + j] * gD;
+      if (c.energy == 1) A[(int64_t)N * lda + col] -= kV * HG * w1[1 + j] * gD;
       for (int r = 0; r < 6; r++) {
         const double *o = w + soot::OUT + 12 * r;
         A[(int64_t)(N + 1 + r) * lda + col] += kV * ((r == j ? exp(x[N + 1 + r]) / c.tau : 0.0) - o[3 + j]);
@@ -639,7 +649,10 @@ __device__ void jacobian(Ctx &c, const double *x, double *A, int lda) {
     dwdT[i] = dT;
   }
   __syncthreads();
-  if (c.energy) {
+  if (c.energy == 2) {  // prescribed temperature: the row V (T - T_in) / tau
+    if (tid == 0) A[(int64_t)N * lda + N] = kV / c.tau;
+    __syncthreads();
+  } else if (c.energy) {
     // energy row: dF_T/dY_m = -mdot Q_in/(S W_m) + V sum_i H_i dwdot_i/dY_m
     double qin = 0.0, dqin = 0.0, tt = 0.0, hE = 0.0;
     for (int i = tid; i < N; i += BS) {

@@ -58,6 +58,7 @@ int lds_limit_bytes() {
 
 struct psr_mech {
   int E, N, I, nnz;
+  double soot_vol = 0.0;  // cm^3 of soot per carbon atom (m_C / rho_s); 0: no soot
   MechDev dev;
   void *blob;  // one device allocation holding every table
 };
@@ -278,6 +279,19 @@ __global__ void __launch_bounds__(kBS) k_persistent(GroupDev g, Opts o, RState *
     write_result(g, c, s, b);
     if (threadIdx.x == 0) states[b] = s;
     __syncthreads();
+  }
+}
+
+// Soot outputs from the moments, one reactor per thread (coalesced over b):
+// f_v = M_1 v_C, N = M_0, d = (6 f_v / (pi N))^(1/3); v_C = m_C / rho_s.
+__global__ void __launch_bounds__(256) k_soot_outputs(int64_t B, int N, const double *__restrict__ x,
+                                                      double *__restrict__ out, double vC) {
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < B; b += (int64_t)gridDim.x * blockDim.x) {
+    const double N0 = exp(x[(int64_t)(N + 1) * B + b]);
+    const double fv = exp(x[(int64_t)(N + 2) * B + b]) * vC;
+    out[b] = fv;
+    out[B + b] = N0;
+    out[2 * B + b] = cbrt(6.0 * fv / (3.14159265358979323846 * N0));
   }
 }
 
@@ -719,6 +733,7 @@ extern "C" psr_status psr_create_mechanism(const psr_mech_desc *d, psr_mech_t *o
     m->dev.KF0 = sd->coag_scale * 2.2 * pow(3.0 * mC / (4.0 * pi * sd->soot_density), 1.0 / 6.0) *
                  sqrt(6.0 * kB / sd->soot_density);
     m->dev.frac = bd + ofrac;
+    m->soot_vol = mC / sd->soot_density;
   }
   *out = m;
   return PSR_OK;
@@ -743,7 +758,8 @@ static psr_status check_cond(psr_mech_t m, const psr_conditions *c) {
   if (c->n_reactors <= 0) return fail(PSR_EINVAL, "n_reactors must be positive");
   if (c->n_reactors > 0x7fffffffLL) return fail(PSR_EUNSUPPORTED, "n_reactors above 2^31-1");
   if (!c->P || !c->tau || !c->T_in || !c->Y_in) return fail(PSR_EINVAL, "null condition pointer");
-  if (m->dev.soot && !c->energy) return fail(PSR_EINVAL, "a soot mechanism needs energy reactors");
+  if (c->energy < 0 || c->energy > 2) return fail(PSR_EINVAL, "energy must be 0, 1 or 2");
+  if (m->dev.soot && !c->energy) return fail(PSR_EINVAL, "a soot mechanism needs a temperature unknown (energy 1 or 2)");
   return PSR_OK;
 }
 
@@ -790,13 +806,13 @@ extern "C" psr_status psr_residual(psr_mech_t m, const psr_conditions *c, const 
   if (st != PSR_OK) return st;
   if (!x || !F) return fail(PSR_EINVAL, "null x or F");
   const int n = n_unknowns(m->dev, c->energy);
-  if (m->dev.packed && n <= 64) {
+  if (m->dev.packed && n <= 64 && c->energy != 2) {
     const size_t lds = wk::align16(psr::wave::tables_bytes(m->N, m->I, m->nnz)) +
                        (size_t)wk::kWR * psr::wave::WArea<64>::species_doubles() * 8;
     if (lds <= (size_t)lds_limit_bytes()) {
       GroupDev g{};
       g.m = m->dev;
-      g.energy = c->energy ? 1 : 0;
+      g.energy = c->energy;
       g.B = c->n_reactors;
       g.P = c->P; g.tau = c->tau; g.Tin = c->T_in; g.Yin = c->Y_in;
       g.x = const_cast<double *>(x);
@@ -811,8 +827,19 @@ extern "C" psr_status psr_residual(psr_mech_t m, const psr_conditions *c, const 
   const size_t lds = layout_bytes(m, c->energy, false, true);
   if (lds > (size_t)lds_limit_bytes()) return fail(PSR_EUNSUPPORTED, "mechanism too large for LDS");
   hipLaunchKernelGGL(k_residual, dim3((unsigned)c->n_reactors), dim3(kBS), lds, (hipStream_t)stream,
-                     m->dev, c->energy ? 1 : 0, c->n_reactors, c->P, c->tau, c->T_in, c->Y_in, x, F,
+                     m->dev, c->energy, c->n_reactors, c->P, c->tau, c->T_in, c->Y_in, x, F,
                      scaled);
+  HIP_OK(hipGetLastError());
+  return PSR_OK;
+}
+
+extern "C" psr_status psr_soot_outputs(psr_mech_t m, int64_t B, const double *x, double *out, void *stream) {
+  if (!m || !x || !out) return fail(PSR_EINVAL, "null argument");
+  if (B < 1) return fail(PSR_EINVAL, "n_reactors must be positive");
+  if (!m->dev.soot) return fail(PSR_EINVAL, "mechanism has no soot model");
+  const int64_t blocks = (B + 255) / 256;
+  const unsigned grid = (unsigned)(blocks < 4096 ? blocks : 4096);
+  hipLaunchKernelGGL(k_soot_outputs, dim3(grid), dim3(256), 0, (hipStream_t)stream, B, m->N, x, out, m->soot_vol);
   HIP_OK(hipGetLastError());
   return PSR_OK;
 }
@@ -825,7 +852,7 @@ extern "C" psr_status psr_jacobian(psr_mech_t m, const psr_conditions *c, const 
   const size_t lds = layout_bytes(m, c->energy, false, true);
   if (lds > (size_t)lds_limit_bytes()) return fail(PSR_EUNSUPPORTED, "mechanism too large for LDS");
   hipLaunchKernelGGL(k_jacobian, dim3((unsigned)c->n_reactors), dim3(kBS), lds, (hipStream_t)stream,
-                     m->dev, c->energy ? 1 : 0, c->n_reactors, c->P, c->tau, c->T_in, c->Y_in, x, J);
+                     m->dev, c->energy, c->n_reactors, c->P, c->tau, c->T_in, c->Y_in, x, J);
   HIP_OK(hipGetLastError());
   return PSR_OK;
 }
@@ -1088,7 +1115,8 @@ struct WavePlan {
 static WavePlan wave_plan(psr_mech_t m, int energy, bool mixed, int engine, int rpw_req = 0) {
   WavePlan w;
   const int n = n_unknowns(m->dev, energy);
-  if (engine == 1 || !m->dev.packed) return w;
+  // the wavefront engine implements the isothermal and energy-balance rows only
+  if (engine == 1 || !m->dev.packed || energy == 2) return w;
   const int NP = wave_np(n);
   if (!NP) return w;
   const size_t tb = wk::wave_area_off(m->N, m->I, m->nnz);
@@ -1308,7 +1336,7 @@ static psr_status prepare_group(const psr_group &g, const psr_solve_opts *o, voi
     return fail(PSR_EUNSUPPORTED, "reactor working set (" + std::to_string(r.lds) +
                                       " B without matrices) exceeds the LDS of one workgroup");
   GroupDev &gd = r.gd;
-  gd.m = g.mech->dev; gd.energy = g.cond.energy ? 1 : 0; gd.B = g.cond.n_reactors;
+  gd.m = g.mech->dev; gd.energy = g.cond.energy; gd.B = g.cond.n_reactors;
   gd.P = g.cond.P; gd.tau = g.cond.tau; gd.Tin = g.cond.T_in; gd.Yin = g.cond.Y_in;
   gd.x = g.x_inout; gd.status = g.status; gd.nlin = g.n_lin;
   char *p = reinterpret_cast<char *>(ws);
@@ -1565,7 +1593,7 @@ std::string tune_key(const psr_group *groups, int32_t n_groups, const psr_solve_
     const psr_mech_t m = groups[gi].mech;
     const int64_t S = std::min<int64_t>(sample, groups[gi].cond.n_reactors);
     k += "/g" + std::to_string(m->N) + "," + std::to_string(m->I) + "," + std::to_string(m->nnz) + "," +
-         std::to_string(m->dev.soot ? 1 : 0) + "," + std::to_string(groups[gi].cond.energy ? 1 : 0) + "," +
+         std::to_string(m->dev.soot ? 1 : 0) + "," + std::to_string(groups[gi].cond.energy) + "," +
          std::to_string(S);
   }
   return k;

@@ -196,3 +196,19 @@ def test_fd_jacobian_rejects_null_arguments_on_the_host(lib):
     for cond in (None, C.byref(c)):
         st = lib.psr_jacobian_fd(None, cond, None, None, None, None)
         assert st == _lib.PSR_EINVAL and "null" in lib.psr_last_error().decode()
+
+
+def test_soot_outputs_and_energy_mode_are_validated_on_the_host(lib):
+    """psr_soot_outputs rejects a null mechanism or buffer; the solve and
+    residual calls reject an energy mode outside 0, 1, 2 (checked before any
+    device work: a null mechanism is reported first, so the mode is checked
+    through the ABI's own argument validation only where no device is
+    needed)."""
+    from paper_2005_11468_amd import _lib
+    buf = (C.c_double * 8)()
+    assert lib.psr_soot_outputs(None, 1, C.cast(buf, C.c_void_p), C.cast(buf, C.c_void_p), None) == _lib.PSR_EINVAL
+    assert b"null" in lib.psr_last_error()
+    import paper_2005_11468_amd as P
+    with pytest.raises(ValueError):
+        P._energy(3)
+    assert [P._energy(e) for e in (False, True, 0, 1, 2)] == [0, 1, 0, 1, 2]
