@@ -277,6 +277,13 @@ typedef struct {
    * steps start from the last root (else the initial guess) when this ends
    * short of the reactor's tau. */
   double ct_ratio, ct_tau_min, ct_min_step;
+  /* persistent scheduler, order in which reactors are taken from the device
+   * queue: 1 = longest residence time first (descending tau, ties by batch
+   * index; a reactor's solve cost grows with tau, so the long solves start
+   * first and the short ones fill the tail), groups of several mechanisms
+   * launched largest n first; 0 = batch order.  The ordering reads tau back
+   * to the host once per call.  Results are bitwise independent of it. */
+  int32_t order;
 } psr_solve_opts;
 
 /* Fill opts with the defaults (FP64, plain scheduler, graph replay on,

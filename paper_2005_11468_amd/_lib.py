@@ -50,7 +50,8 @@ class SolveOpts(C.Structure):
                 ("atol_lnM", C.c_double), ("ts_atol_lnM", C.c_double),
                 ("rpw", C.c_int32), ("grid_per_cu", C.c_int32),
                 ("lnM_step", C.c_double), ("ct_ratio", C.c_double),
-                ("ct_tau_min", C.c_double), ("ct_min_step", C.c_double)]
+                ("ct_tau_min", C.c_double), ("ct_min_step", C.c_double),
+                ("order", C.c_int32)]
 
 
 class Group(C.Structure):

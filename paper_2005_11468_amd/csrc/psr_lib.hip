@@ -205,6 +205,7 @@ struct GroupDev {
   double *x;       // [n][B]
   int *status;     // [B]
   int *nlin;       // [B] or null
+  const int *order;  // persistent queue position -> reactor index, or null (batch order)
 };
 
 __device__ inline void write_result(const GroupDev &g, const Ctx &c, const RState &s, int64_t b) {
@@ -264,9 +265,10 @@ __global__ void __launch_bounds__(kBS) k_persistent(GroupDev g, Opts o, RState *
   for (;;) {
     if (threadIdx.x == 0) *next = atomicAdd(queue, 1);
     __syncthreads();
-    const int64_t b = *next;
+    const int64_t pos = *next;
     __syncthreads();
-    if (b >= g.B) break;
+    if (pos >= g.B) break;
+    const int64_t b = g.order ? g.order[pos] : pos;
     Ctx c = make_ctx(g.m, L, g.energy, g.P[b], g.tau[b], g.Tin[b], lds);
     if (matws) c.mat = matws + (int64_t)blockIdx.x * L.mat_total;  // this workgroup's HBM matrices
     load_inlet<kBS>(c, g.Yin, g.B, b);
@@ -370,6 +372,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
     if (lane == 0) b = atomicAdd(queue, 1);
     b = bcast(b, 0);
     if (b >= g.B) break;
+    if (g.order) b = g.order[b];
     WCtx c;
     make_wctx<NP, MIXED>(c, t, g, b);
     WState<NP, MIXED> r;
@@ -532,6 +535,7 @@ extern "C" void psr_default_opts(psr_solve_opts *o) {
   o->ct_ratio = 10.0;
   o->ct_tau_min = 1e-6;
   o->ct_min_step = 0.05;
+  o->order = 1;
 }
 
 // Lagrange basis polynomial l over the nodes 0..m-1, at p.
@@ -1273,6 +1277,7 @@ static size_t group_ws(const psr_group &g, const psr_solve_opts *o) {
   const bool mixed = o->precision == PSR_MIXED;
   block_layout(g.mech, g.cond.energy, mixed, L);
   size_t bytes = align256(sizeof(RState) * (size_t)g.cond.n_reactors) + 256;
+  if (o->scheduler == PSR_PERSISTENT) bytes += align256(sizeof(int) * (size_t)g.cond.n_reactors);  // queue order
   const WavePlan w = wave_plan(g.mech, g.cond.energy, mixed, o->engine, o->rpw);
   if (o->scheduler == PSR_PLAIN)
     bytes += align256((size_t)(w.NP ? w.stride : L.persist + L.mat_total) * 8 * g.cond.n_reactors);
@@ -1305,7 +1310,8 @@ static psr_status check_opts(const psr_solve_opts *o) {
       o->use_graph > 1 || !(o->refine_tol > 0 && o->refine_tol < 1) || !(o->atol_lnM >= 0) ||
       !(o->ts_atol_lnM >= 0) || !(o->rpw == 0 || o->rpw == 1 || o->rpw == 2 || o->rpw == 4) ||
       o->grid_per_cu < 0 || o->grid_per_cu > 32 || !(o->lnM_step > 0) ||
-      !(o->ct_ratio >= 0) || !(o->ct_tau_min > 0) || !(o->ct_min_step > 0))
+      !(o->ct_ratio >= 0) || !(o->ct_tau_min > 0) || !(o->ct_min_step > 0) || o->order < 0 ||
+      o->order > 1)
     return fail(PSR_EINVAL, "option out of range");
   return PSR_OK;
 }
@@ -1320,8 +1326,11 @@ struct GroupRun {
   bool mixed = false;
   RState *states = nullptr;
   int *counters = nullptr;
+  int *order = nullptr;  // persistent scheduler: device queue order [B]
   double *area = nullptr;
   int rounds = 0;
+  std::vector<double> host_tau;  // host copies for the queue order (alive until the call returns)
+  std::vector<int> host_order;
 };
 
 static psr_status prepare_group(const psr_group &g, const psr_solve_opts *o, void *ws, GroupRun &r) {
@@ -1339,12 +1348,35 @@ static psr_status prepare_group(const psr_group &g, const psr_solve_opts *o, voi
   gd.m = g.mech->dev; gd.energy = g.cond.energy; gd.B = g.cond.n_reactors;
   gd.P = g.cond.P; gd.tau = g.cond.tau; gd.Tin = g.cond.T_in; gd.Yin = g.cond.Y_in;
   gd.x = g.x_inout; gd.status = g.status; gd.nlin = g.n_lin;
+  gd.order = nullptr;
   char *p = reinterpret_cast<char *>(ws);
   r.states = reinterpret_cast<RState *>(p);
   p += align256(sizeof(RState) * (size_t)gd.B);
   r.counters = reinterpret_cast<int *>(p);
   p += 256;
+  if (o->scheduler == PSR_PERSISTENT) {
+    r.order = reinterpret_cast<int *>(p);
+    p += align256(sizeof(int) * (size_t)gd.B);
+  }
   r.area = reinterpret_cast<double *>(p);
+  return PSR_OK;
+}
+
+// Device queue order of a persistent group: longest residence time first
+// (ties by batch index; tau that is not a positive finite number goes last).
+// Reads tau back on `stream` (synchronising it) and uploads the permutation.
+static psr_status queue_order(GroupRun &r, hipStream_t stream) {
+  const int64_t B = r.gd.B;
+  r.host_tau.resize(B);
+  r.host_order.resize(B);
+  HIP_OK(hipMemcpyAsync(r.host_tau.data(), r.gd.tau, sizeof(double) * B, hipMemcpyDeviceToHost, stream));
+  HIP_OK(hipStreamSynchronize(stream));
+  std::vector<double> &t = r.host_tau;
+  for (double &v : t) v = (v > 0.0 && v < HUGE_VAL) ? v : -1.0;
+  for (int64_t i = 0; i < B; i++) r.host_order[i] = (int)i;
+  std::stable_sort(r.host_order.begin(), r.host_order.end(), [&](int a, int b) { return t[a] > t[b]; });
+  HIP_OK(hipMemcpyAsync(r.order, r.host_order.data(), sizeof(int) * B, hipMemcpyHostToDevice, stream));
+  r.gd.order = r.order;
   return PSR_OK;
 }
 
@@ -1353,6 +1385,10 @@ static psr_status prepare_group(const psr_group &g, const psr_solve_opts *o, voi
 // the host and returns when every reactor has retired.
 static psr_status launch_group(GroupRun &r, const psr_solve_opts *o, hipStream_t stream) {
   const Opts od = to_dev_opts(o);
+  if (o->scheduler == PSR_PERSISTENT && o->order) {
+    const psr_status st = queue_order(r, stream);
+    if (st != PSR_OK) return st;
+  }
   const GroupDev &gd = r.gd;
   const int64_t B = gd.B;
   const bool mixed = r.mixed;
@@ -1463,7 +1499,16 @@ extern "C" psr_status psr_solve_batch(const psr_group *groups, int32_t n_groups,
     int dev = 0;
     HIP_OK(hipGetDevice(&dev));
     std::vector<hipEvent_t> done(n_groups);
-    for (int gi = 0; gi < n_groups; gi++) {
+    // launch order: largest systems first when ordering by cost
+    std::vector<int> seq(n_groups);
+    for (int gi = 0; gi < n_groups; gi++) seq[gi] = gi;
+    if (opts->order)
+      std::stable_sort(seq.begin(), seq.end(), [&](int a, int b) {
+        return n_unknowns(groups[a].mech->dev, groups[a].cond.energy) >
+               n_unknowns(groups[b].mech->dev, groups[b].cond.energy);
+      });
+    for (int si = 0; si < n_groups; si++) {
+      const int gi = seq[si];
       hipStream_t gs;
       st = group_stream(dev, gi, &gs);
       if (st != PSR_OK) return st;

@@ -156,10 +156,11 @@ __device__ inline void solve_scaled32(const Ctx &c, const float *A32, const int 
 // Mixed: float solve + FP64 iterative refinement against the unfactored
 // FP64 matrix (r = b - A z in FP64); refinement stops when the correction
 // is below tol of |z| in max norm; if the correction shrinks by less
-// than half, or max_refine sweeps do not reach that, the matrix is
-// refactored in FP64 for the rest of this linearisation.
+// than half, or max_refine sweeps do not reach that, the call returns true
+// (s.fb64 set): the caller refactors the matrix in FP64 for the rest of this
+// linearisation and solves again.
 template <int BS, bool MIXED, bool BIG>
-__device__ void solve_round(const Ctx &c, const Opts &o, RState &s, const double *b, double *z, double tol) {
+__device__ bool solve_round(const Ctx &c, const Opts &o, RState &s, const double *b, double *z, double tol) {
   const int n = c.n, lda = c.L.lda;
   double *red = c.p(c.L.red);
   double *A64 = c.A64();
@@ -168,10 +169,10 @@ __device__ void solve_round(const Ctx &c, const Opts &o, RState &s, const double
     const double *rs = c.p(c.L.rs), *cs = c.p(c.L.cs);
     for (int i = threadIdx.x; i < n; i += BS) z[i] = rs[i] * b[i];
     __syncthreads();
-    lu_solve<BS, double>(A64, n, lda, piv, z);
+    if (!s.sing) lu_solve<BS, double>(A64, n, lda, piv, z);
     for (int i = threadIdx.x; i < n; i += BS) z[i] *= cs[i];
     __syncthreads();
-    return;
+    return false;
   }
   const float *A32 = c.A32();
   const double *rs = c.p(c.L.rs), *cs = c.p(c.L.cs);
@@ -201,18 +202,12 @@ __device__ void solve_round(const Ctx &c, const Opts &o, RState &s, const double
     if (!(dn <= 0.5 * prev)) break;
     prev = dn;
   }
-  if (ok) return;
+  if (ok) return false;
   // FP64 fallback for this matrix
   s.fb64 = 1;
   s.n_fb64++;
   note_fallback(s);
-  const int info = factor64<BS, BIG>(c, A64, piv, red);
-  s.sing = info != 0;
-  for (int i = threadIdx.x; i < n; i += BS) z[i] = rs[i] * bb[i];
-  __syncthreads();
-  if (!s.sing) lu_solve<BS, double>(A64, n, lda, piv, z);
-  for (int i = threadIdx.x; i < n; i += BS) z[i] *= cs[i];
-  __syncthreads();
+  return true;
 }
 
 // ---------------------------------------------------------------- rounds
@@ -352,6 +347,7 @@ __device__ void round_step(Ctx &c, const Opts &o, RState &s) {
   const int ph = s.phase;
   const bool lin = (ph == PH_NW_BASE || ph == PH_TS1);
   const bool nw = (ph == PH_NW_BASE || ph == PH_NW_TRIAL);
+  bool want64 = false;  // an FP64 factorisation of A64 is due
 
   // a Newton attempt of the continuation evaluates at its own residence time
   const double tau = c.tau;
@@ -374,7 +370,7 @@ __device__ void round_step(Ctx &c, const Opts &o, RState &s) {
         s.stick--;
         s.fb64 = 1;
         s.n_fb64++;
-        s.sing = factor64<BS, BIG>(c, A64, piv, red) != 0;
+        want64 = true;
       } else if (MIXED) {
         const int info = factor_mixed<BS, BIG>(c, A64, c.A32(), piv,
                                           c.p(L.rs), c.p(L.cs), red);
@@ -382,37 +378,53 @@ __device__ void round_step(Ctx &c, const Opts &o, RState &s) {
           s.fb64 = 1;
           s.n_fb64++;
           note_fallback(s);
-          s.sing = factor64<BS, BIG>(c, A64, piv, red) != 0;
+          want64 = true;
         }
       } else {
-        s.sing = factor64<BS, BIG>(c, A64, piv, red) != 0;
+        want64 = true;
       }
     }
   }
   c.tau = tau;
-  const bool skip = lin && (!s.fin || s.sing);
-  if (!skip) {
-    // right-hand side of this round, formed in place of the residual
-    for (int i = threadIdx.x; i < n; i += BS) {
-      double v;
-      if (ph == PH_TS1) v = -G[i] / (kGamma * s.h);
-      else if (ph == PH_TS2) v = (-G[i] - 2.0 * M[i] * d[i]) / (kGamma * s.h);
-      else v = -G[i];
-      G[i] = v;
+  // Every FP64 factorisation of the round (the linearisation's, and the
+  // refactorisation after a float solve whose refinement stalls) goes
+  // through the one call site at the top of this loop: one inlined copy of
+  // the blocked LU keeps the kernel's register and scratch use down.
+  bool skip = false, first = true;
+  double *out = (ph == PH_NW_BASE || ph == PH_TS1) ? d : t;
+  double tol = o.refine_tol;
+  for (;;) {
+    if (want64) {
+      s.sing = factor64<BS, BIG>(c, A64, piv, red) != 0;
+      want64 = false;
     }
-    __syncthreads();
-    double *out = (ph == PH_NW_BASE || ph == PH_TS1) ? d : t;
-    double tol = o.refine_tol;
-    for (;;) {
-      solve_round<BS, MIXED, BIG>(c, o, s, G, out, tol);
-      // a Newton step that would end the solve must rest on a tightly refined solve
-      if (MIXED && ph == PH_NW_BASE && !s.sing && !s.fb64 && tol > kFinalRefine && sres <= o.ftol &&
-          all_finite<BS>(out, n, red) && newton_norm<BS>(c, o, xnw, out, red) <= 1.0) {
-        tol = kFinalRefine;
-        continue;
+    if (first) {
+      first = false;
+      skip = lin && (!s.fin || s.sing);
+      if (skip) break;
+      // right-hand side of this round, formed in place of the residual
+      for (int i = threadIdx.x; i < n; i += BS) {
+        double v;
+        if (ph == PH_TS1) v = -G[i] / (kGamma * s.h);
+        else if (ph == PH_TS2) v = (-G[i] - 2.0 * M[i] * d[i]) / (kGamma * s.h);
+        else v = -G[i];
+        G[i] = v;
       }
-      break;
+      __syncthreads();
     }
+    if (solve_round<BS, MIXED, BIG>(c, o, s, G, out, tol)) {
+      want64 = true;  // refactor in FP64, then solve again
+      continue;
+    }
+    // a Newton step that would end the solve must rest on a tightly refined solve
+    if (MIXED && ph == PH_NW_BASE && !s.sing && !s.fb64 && tol > kFinalRefine && sres <= o.ftol &&
+        all_finite<BS>(out, n, red) && newton_norm<BS>(c, o, xnw, out, red) <= 1.0) {
+      tol = kFinalRefine;
+      continue;
+    }
+    break;
+  }
+  if (!skip) {
     if (MIXED && s.sing) {  // an FP64 refactorisation found the matrix singular
       if (ph == PH_NW_BASE) { nw_failed<BS>(c, o, s); return; }
       if (ph == PH_TS1) { s.n_lin += 2; reject_ts<BS>(c, o, s, true, 0.0); return; }

@@ -174,3 +174,18 @@ def test_multi_group_stats_match_status_arrays(P, scheduler):
     assert st.converged == int((status == 0).sum())
     assert st.lin_total == int(nlin.sum())
     assert st.lin_max == int(nlin.max())
+
+
+@pytest.mark.parametrize("engine", [1, 2])
+def test_queue_order_leaves_results_bitwise_unchanged(P, engine):
+    """The persistent scheduler's longest-residence-time-first queue order
+    changes only which reactor runs when: x, status and n_lin are bitwise
+    those of batch order."""
+    from psr_inputs import workload
+    mech, cond, x0, energy = workload("energy", 96)
+    M = P.Mechanism(mech)
+    a = solve_gpu(M, cond, x0, energy, scheduler=1, engine=engine, precision=1, order=0)
+    b = solve_gpu(M, cond, x0, energy, scheduler=1, engine=engine, precision=1, order=1)
+    for u, v in zip(a[:3], b[:3]):
+        assert np.array_equal(u, v)
+    assert a[3].converged == b[3].converged and a[3].lin_total == b[3].lin_total

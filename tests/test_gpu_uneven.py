@@ -103,3 +103,13 @@ def test_concurrent_groups_match_separate_calls(P, groups):
         (xb, sb, nb), = _solve_all(P, [g], precision=0, scheduler=P.PSR_PERSISTENT)[0]
         assert np.array_equal(sa, sb) and np.array_equal(na, nb)
         assert np.array_equal(xa, xb)
+
+
+def test_queue_order_leaves_groups_bitwise_unchanged(P, groups):
+    """Three mechanisms in one persistent call, taken longest residence time
+    first and launched largest n first, against batch order: bitwise equal."""
+    a, _ = _solve_all(P, groups, precision=1, scheduler=P.PSR_PERSISTENT, order=0)
+    b, _ = _solve_all(P, groups, precision=1, scheduler=P.PSR_PERSISTENT, order=1)
+    for (xa, sa, na), (xb, sb, nb) in zip(a, b):
+        assert np.array_equal(sa, sb) and np.array_equal(na, nb)
+        assert np.array_equal(xa, xb)
