@@ -369,8 +369,10 @@ def cpu_model():
 def uneven(P, steps=1, warmup=1, sample=64, cores=16):
     """The three-mechanism workload: 65536 reactors (30/200, 100/600, 200/1200
     species / reactions, 32768 / 22938 / 9830) in one mixed-precision
-    persistent psr_solve_batch call; oracle parity on a seeded sample of each
-    group over its whole residence-time range."""
+    persistent psr_solve_batch call, which runs as one fused launch over one
+    device queue (longest residence time first, largest n first); oracle
+    parity on a seeded sample of each group over its whole residence-time
+    range."""
     import torch
     from psr_inputs import uneven_workload
     from tests.gpu_util import cond_dev, dev

@@ -281,8 +281,15 @@ typedef struct {
    * queue: 1 = longest residence time first (descending tau, ties by batch
    * index; a reactor's solve cost grows with tau, so the long solves start
    * first and the short ones fill the tail), groups of several mechanisms
-   * launched largest n first; 0 = batch order.  The ordering reads tau back
-   * to the host once per call.  Results are bitwise independent of it. */
+   * taken largest n first; 0 = batch order.  The ordering reads tau back
+   * to the host once per call.  Results are bitwise independent of it.
+   * A persistent call with 2 to 4 groups, at most one of them on the
+   * wavefront engine, and the automatic launch shape (engine, rpw and
+   * grid_per_cu all 0) runs as ONE launch over one device queue: the
+   * workgroup-engine groups' reactors first, then the wavefront-engine
+   * group's, each workgroup switching to four independent wavefronts when it
+   * reaches them.  Other multi-group persistent calls launch one kernel per
+   * group, side by side.  Both give the same bits per reactor. */
   int32_t order;
 } psr_solve_opts;
 

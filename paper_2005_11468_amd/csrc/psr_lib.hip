@@ -65,6 +65,17 @@ struct psr_mech {
 
 // ------------------------------------------------------------------ kernels
 
+// Reactor of a one-workgroup-per-reactor launch.  Workgroups are dealt to
+// the 8 XCDs round-robin (workgroup i to XCD i mod 8); numbering the reactors
+// so that the workgroups of one XCD take consecutive reactors keeps the
+// [var][reactor] lines that neighbouring reactors share in one XCD's L2.
+// A bijection of [0, G).
+__device__ inline int64_t xcd_reactor(int64_t blk, int64_t G) {
+  constexpr int64_t kX = 8;
+  const int64_t x = blk % kX, j = blk / kX, q = G / kX, r = G % kX;
+  return x * q + (x < r ? x : r) + j;
+}
+
 __device__ inline Ctx make_ctx(const MechDev &m, const Layout &L, int energy, double P, double tau,
                                double Tin, double *base) {
   Ctx c;
@@ -86,7 +97,7 @@ __global__ void __launch_bounds__(kBS) k_residual(MechDev m, int energy, int64_t
                                                   const double *Yin, const double *x, double *F,
                                                   double *scaled) {
   extern __shared__ double lds[];
-  const int64_t b = blockIdx.x;
+  const int64_t b = xcd_reactor(blockIdx.x, gridDim.x);
   Layout L;
   L.make(m.N, m.I, n_unknowns(m, energy), false, kBS, true);  // no matrix needed
   Ctx c = make_ctx(m, L, energy, P[b], tau[b], Tin[b], lds);
@@ -103,7 +114,7 @@ __global__ void __launch_bounds__(kBS) k_jacobian(MechDev m, int energy, int64_t
                                                   const double *tau, const double *Tin,
                                                   const double *Yin, const double *x, double *J) {
   extern __shared__ double lds[];
-  const int64_t b = blockIdx.x;
+  const int64_t b = xcd_reactor(blockIdx.x, gridDim.x);
   Layout L;
   L.make(m.N, m.I, n_unknowns(m, energy), false, kBS, true);  // the matrix is the output
   Ctx c = make_ctx(m, L, energy, P[b], tau[b], Tin[b], lds);
@@ -382,6 +393,105 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
   }
 }
 
+// ------------------------------------------------ fused persistent launch
+
+// Several groups (mechanisms) of one persistent solve in one launch over one
+// device queue.  Queue positions [start_g, start_g + B_g) belong to group g;
+// the workgroup-engine groups come first (largest n first), at most one
+// wavefront-engine group last.  A workgroup takes positions one at a time and
+// solves the reactor with all its threads; once it draws a position of the
+// wavefront-engine group it stages that group's tables in its LDS and from
+// then on each of its four wavefronts takes positions on its own.
+constexpr int kMaxFused = 4;
+
+struct FusedGroup {
+  GroupDev g;
+  RState *states;
+  int64_t start;  // first queue position of the group
+  int wave;       // 1: wavefront engine
+  int split;      // workgroup engine: matrices in HBM
+};
+
+struct FusedDev {
+  FusedGroup grp[kMaxFused];
+  int ng;
+  int64_t total;       // positions in the queue (reactors of every group)
+  double *matws;       // HBM matrices of the workgroup engine, mat_stride doubles per workgroup
+  int64_t mat_stride;
+  int next_off;        // LDS byte offset of the position broadcast slot
+};
+
+template <int NP, bool MIXED>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_fused(FusedDev fd, Opts og, int *queue) {
+  extern __shared__ double lds[];
+  char *base = reinterpret_cast<char *>(lds);
+  int *next = reinterpret_cast<int *>(base + fd.next_off);
+  int p = 0;
+  int gi = 0;
+  for (;;) {
+    if (threadIdx.x == 0) *next = atomicAdd(queue, 1);
+    __syncthreads();
+    p = *next;
+    __syncthreads();
+    if (p >= fd.total) return;
+    gi = 0;
+    while (gi + 1 < fd.ng && p >= fd.grp[gi + 1].start) gi++;
+    if (fd.grp[gi].wave) break;  // the same for every thread: p is shared
+    const GroupDev &g = fd.grp[gi].g;
+    Layout L;
+    L.make(g.m.N, g.m.I, n_unknowns(g.m, g.energy), MIXED, kBS, fd.grp[gi].split != 0);
+    const int64_t pos = p - fd.grp[gi].start;
+    const int64_t b = g.order ? g.order[pos] : pos;
+    Ctx c = make_ctx(g.m, L, g.energy, g.P[b], g.tau[b], g.Tin[b], lds);
+    if (fd.grp[gi].split) c.mat = fd.matws + (int64_t)blockIdx.x * fd.mat_stride;
+    load_inlet<kBS>(c, g.Yin, g.B, b);
+    double *xl = c.p(L.x);
+    for (int i = threadIdx.x; i < c.n; i += kBS) xl[i] = g.x[(int64_t)i * g.B + b];
+    __syncthreads();
+    RState s;
+    init_state<kBS>(c, og, s);
+    while (s.phase != PH_DONE) round_step<kBS, MIXED, true>(c, og, s);
+    write_result(g, c, s, b);
+    if (threadIdx.x == 0) fd.grp[gi].states[b] = s;
+    __syncthreads();
+  }
+  if constexpr (NP > 0) {
+    const GroupDev &g = fd.grp[gi].g;
+    RState *states = fd.grp[gi].states;
+    const int64_t start = fd.grp[gi].start;
+    const Tables t = stage_tables(g.m, base, g.m.packed);
+    Opts *ol = reinterpret_cast<Opts *>(base + wave_opts_off(g.m.N, g.m.I, g.m.nnz));
+    if (threadIdx.x == 0) *ol = og;
+    __syncthreads();
+    const Opts &o = *ol;
+    const int n = n_unknowns(g.m, g.energy);
+    WArea<NP> A;
+    A.at(reinterpret_cast<double *>(base + wave_area_off(g.m.N, g.m.I, g.m.nnz)) +
+             (size_t)wave_id() * WArea<NP>::doubles(n), n);
+    const int lane = lane_id();
+    int q = p;  // wavefront 0 keeps the position its workgroup drew
+    if (wave_id() != 0) {
+      int v = 0;
+      if (lane == 0) v = atomicAdd(queue, 1);
+      q = bcast(v, 0);
+    }
+    while (q < fd.total) {
+      const int64_t pos = q - start;
+      const int64_t b = g.order ? g.order[pos] : pos;
+      WCtx c;
+      make_wctx<NP, MIXED>(c, t, g, b);
+      WState<NP, MIXED> r;
+      init_w<NP, MIXED>(c, o, r, lane < n ? g.x[(int64_t)lane * g.B + b] : 0.0);
+      while (r.s.phase != PH_DONE) w_round<NP, MIXED>(c, A, o, r);
+      write_result_w<NP, MIXED>(g, c, r, states, b);
+      int v = 0;
+      if (lane == 0) v = atomicAdd(queue, 1);
+      q = bcast(v, 0);
+    }
+  }
+}
+
 template <int NP, bool MIXED>
 __device__ inline void save_w(const WCtx &c, const WArea<NP> &A, const WState<NP, MIXED> &r, double *ar) {
   const int lane = lane_id(), n = c.n;
@@ -485,7 +595,12 @@ k_wresidual(GroupDev g, double *F, double *scaled) {
   WArea<64> A;
   A.at_species(reinterpret_cast<double *>(base + toff) + (size_t)wave_id() * WArea<64>::species_doubles());
   const int lane = lane_id();
-  for (int64_t b = (int64_t)blockIdx.x * kWR + wave_id(); b < g.B; b += (int64_t)gridDim.x * kWR) {
+  // each workgroup walks one contiguous range of reactors, kWR at a time:
+  // the [var][reactor] lines its wavefronts read (and write) are shared by
+  // neighbouring reactors, which then stay on one CU and one XCD's L2
+  const int64_t per = ((g.B + gridDim.x - 1) / gridDim.x + kWR - 1) / kWR * kWR;
+  const int64_t b0 = (int64_t)blockIdx.x * per, b1 = b0 + per < g.B ? b0 + per : g.B;
+  for (int64_t b = b0 + wave_id(); b < b1; b += kWR) {
     WCtx c;
     make_wctx<64, false>(c, t, g, b);
     const double x = lane < n ? g.x[(int64_t)lane * g.B + b] : 0.0;
@@ -1286,6 +1401,67 @@ static size_t group_ws(const psr_group &g, const psr_solve_opts *o) {
   return bytes;
 }
 
+// One fused launch for the groups of a persistent solve (wk::k_fused): 2 to
+// kMaxFused groups, at most one on the wavefront engine (four wavefronts per
+// workgroup), automatic launch shape.  lds: the largest group's LDS plus the
+// broadcast slot; mat_stride: the largest HBM matrix area of a workgroup-
+// engine group; grid: resident workgroups.
+struct FusedPlan {
+  bool ok = false;
+  int NP = 0;
+  size_t lds = 0;
+  int next_off = 0;
+  int64_t grid = 0, mat_stride = 0;
+};
+
+static FusedPlan fused_plan(const psr_group *groups, int32_t n_groups, const psr_solve_opts *o) {
+  FusedPlan f;
+  if (o->scheduler != PSR_PERSISTENT || n_groups < 2 || n_groups > wk::kMaxFused) return f;
+  if (o->engine != 0 || o->rpw != 0 || o->grid_per_cu != 0) return f;
+  const bool mixed = o->precision == PSR_MIXED;
+  int waves = 0;
+  size_t lds = 0;
+  int64_t mat = 0, total = 0;
+  for (int gi = 0; gi < n_groups; gi++) {
+    const psr_group &g = groups[gi];
+    if (!g.mech || g.cond.n_reactors <= 0) return f;
+    total += g.cond.n_reactors;
+    const WavePlan w = wave_plan(g.mech, g.cond.energy, mixed, 0, 4);
+    if (w.NP) {
+      if (w.rpw != 4) return f;
+      waves++;
+      f.NP = w.NP;
+      lds = std::max(lds, w.lds);
+    } else {
+      Layout L;
+      if (!block_layout(g.mech, g.cond.energy, mixed, L)) return f;
+      lds = std::max(lds, (size_t)L.total * 8);
+      if (L.split) mat = std::max<int64_t>(mat, L.mat_total);
+    }
+  }
+  if (waves > 1 || total > 0x7fffffffLL) return f;
+  f.next_off = (int)wk::align16(lds);
+  f.lds = (size_t)f.next_off + 16;
+  if (f.lds > (size_t)lds_limit_bytes()) return f;
+  int dev = 0, ncu = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return f;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return f;
+  hipError_t e;
+#define PSR_FUSED_OCC(NP_, M_) hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wk::k_fused<NP_, M_>, 256, f.lds)
+  switch (f.NP) {
+    case 0: e = mixed ? PSR_FUSED_OCC(0, true) : PSR_FUSED_OCC(0, false); break;
+    case 16: e = mixed ? PSR_FUSED_OCC(16, true) : PSR_FUSED_OCC(16, false); break;
+    case 32: e = mixed ? PSR_FUSED_OCC(32, true) : PSR_FUSED_OCC(32, false); break;
+    default: e = mixed ? PSR_FUSED_OCC(64, true) : PSR_FUSED_OCC(64, false); break;
+  }
+#undef PSR_FUSED_OCC
+  if (e != hipSuccess || per_cu < 1) return f;
+  f.grid = std::min<int64_t>(total, (int64_t)ncu * per_cu);
+  f.mat_stride = mat;
+  f.ok = true;
+  return f;
+}
+
 extern "C" size_t psr_workspace_bytes(const psr_group *groups, int32_t n_groups,
                                       const psr_solve_opts *opts) {
   if (!groups || n_groups <= 0 || !opts) return 0;
@@ -1296,6 +1472,8 @@ extern "C" size_t psr_workspace_bytes(const psr_group *groups, int32_t n_groups,
     mx = std::max(mx, b);
     sum += align256(b);
   }
+  const FusedPlan f = fused_plan(groups, n_groups, opts);
+  if (f.ok) sum += 256 + align256((size_t)f.grid * f.mat_stride * 8);  // queue counter, HBM matrices
   return concurrent_groups(n_groups, opts) ? sum : mx;
 }
 
@@ -1491,11 +1669,61 @@ extern "C" psr_status psr_solve_batch(const psr_group *groups, int32_t n_groups,
     if (st != PSR_OK) return st;
     if (conc) region += align256(group_ws(groups[gi], opts));
   }
+  const FusedPlan fp = fused_plan(groups, n_groups, opts);
   hipEvent_t e0, e1;
   HIP_OK(hipEventCreate(&e0));
   HIP_OK(hipEventCreate(&e1));
   HIP_OK(hipEventRecord(e0, cs));
-  if (conc) {
+  if (fp.ok) {
+    // every group in one launch over one queue: workgroup-engine groups
+    // largest n first, then the wavefront-engine group
+    int *fcounter = reinterpret_cast<int *>(region);
+    double *fmat = reinterpret_cast<double *>(region + 256);
+    std::vector<int> seq;
+    for (int gi = 0; gi < n_groups; gi++)
+      if (!runs[gi].wplan.NP) seq.push_back(gi);
+    std::stable_sort(seq.begin(), seq.end(), [&](int a, int b) {
+      return n_unknowns(groups[a].mech->dev, groups[a].cond.energy) >
+             n_unknowns(groups[b].mech->dev, groups[b].cond.energy);
+    });
+    for (int gi = 0; gi < n_groups; gi++)
+      if (runs[gi].wplan.NP) seq.push_back(gi);
+    wk::FusedDev fd{};
+    int64_t start = 0;
+    for (int k = 0; k < n_groups; k++) {
+      GroupRun &r = runs[seq[k]];
+      if (opts->order) {
+        st = queue_order(r, cs);
+        if (st != PSR_OK) return st;
+      }
+      fd.grp[k].g = r.gd;
+      fd.grp[k].states = r.states;
+      fd.grp[k].start = start;
+      fd.grp[k].wave = r.wplan.NP ? 1 : 0;
+      fd.grp[k].split = r.L.split;
+      start += r.gd.B;
+    }
+    fd.ng = n_groups;
+    fd.total = start;
+    fd.matws = fmat;
+    fd.mat_stride = fp.mat_stride;
+    fd.next_off = fp.next_off;
+    const Opts od = to_dev_opts(opts);
+    const bool mixed = opts->precision == PSR_MIXED;
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, cs, fcounter, 64);
+    const dim3 grid((unsigned)fp.grid), blk(256);
+#define PSR_FUSED(NP_, M_) hipLaunchKernelGGL((wk::k_fused<NP_, M_>), grid, blk, fp.lds, cs, fd, od, fcounter)
+    switch (fp.NP) {
+      case 0: if (mixed) PSR_FUSED(0, true); else PSR_FUSED(0, false); break;
+      case 16: if (mixed) PSR_FUSED(16, true); else PSR_FUSED(16, false); break;
+      case 32: if (mixed) PSR_FUSED(32, true); else PSR_FUSED(32, false); break;
+      default: if (mixed) PSR_FUSED(64, true); else PSR_FUSED(64, false); break;
+    }
+#undef PSR_FUSED
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipEventRecord(e1, cs));
+    HIP_OK(hipEventSynchronize(e1));
+  } else if (conc) {
     int dev = 0;
     HIP_OK(hipGetDevice(&dev));
     std::vector<hipEvent_t> done(n_groups);

@@ -113,3 +113,17 @@ def test_queue_order_leaves_groups_bitwise_unchanged(P, groups):
     for (xa, sa, na), (xb, sb, nb) in zip(a, b):
         assert np.array_equal(sa, sb) and np.array_equal(na, nb)
         assert np.array_equal(xa, xb)
+
+
+def test_fused_launch_matches_per_group_launches(P, groups):
+    """A persistent call over several mechanisms runs as one launch over one
+    device queue (workgroup-engine groups, then the wavefront-engine group);
+    asking for an explicit launch shape keeps one launch per group.  Both give
+    the same bits per reactor, and the same totals."""
+    a, sa_ = _solve_all(P, groups, precision=1, scheduler=P.PSR_PERSISTENT)
+    b, sb_ = _solve_all(P, groups, precision=1, scheduler=P.PSR_PERSISTENT, rpw=4)
+    for (xa, sa, na), (xb, sb, nb) in zip(a, b):
+        assert np.array_equal(sa, sb) and np.array_equal(na, nb)
+        assert np.array_equal(xa, xb)
+    assert sa_.converged == sb_.converged and sa_.lin_total == sb_.lin_total
+    assert sa_.fp64_fallbacks == sb_.fp64_fallbacks
