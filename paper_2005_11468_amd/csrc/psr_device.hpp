@@ -764,6 +764,7 @@ __device__ int lu_factor(T *A, int n, int lda, int *piv, double *red) {
 // lu_factor (unit-lower L below the diagonal, LAPACK pivots).  BS must be
 // 256.  red: LDS scratch of at least 24 doubles; pan: LDS scratch of at
 // least 17 n floats.  Returns 0 or k+1.
+typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 template <int BS>
@@ -905,12 +906,11 @@ __device__ __forceinline__ int lu_factor_mfma32(float *A, int n, int lda, int *p
 // Blocked right-looking FP64 LU with partial pivoting for matrices kept in
 // HBM (64 < n <= BS), panel width 16.  Same panel as lu_factor_mfma32 (copied
 // to LDS, block argmax with the first-maximum rule, row interchange and
-// rank-one update per column), then one column per thread: the panel's
-// interchanges, U12 = L11^-1 A12 by forward substitution (kept in
-// registers) and the trailing update A22 -= L21 U12 of that column, reading
-// L21 from the panel in LDS.  The trailing matrix is read and written once
-// per panel instead of once per column.  pan: LDS scratch of at least 17 n
-// doubles.  Returns 0 or k+1.
+// rank-one update per column), then one column per thread for the panel's
+// interchanges and U12 = L11^-1 A12 (forward substitution), then the trailing
+// update A22 -= L21 U12 on the FP64 matrix cores in 16 x 16 tiles.  The
+// trailing matrix is read and written once per panel.  pan: LDS scratch of at
+// least 17 n doubles.  Returns 0 or k+1.
 template <int BS>
 __device__ __forceinline__ int lu_factor_blocked64(double *A, int n, int lda, int *piv, double *red, double *pan) {
   static_assert(BS == 256, "one panel row and one column per thread");
@@ -993,23 +993,55 @@ __device__ __forceinline__ int lu_factor_blocked64(double *A, int n, int lda, in
 #pragma unroll
         for (int i = 0; i < 16; i++)
           if (i < kb) A[(int64_t)(k0 + i) * lda + c] = u[i];
-        // trailing update of this column, four rows in flight
-        for (int i0 = R0; i0 < n; i0 += 4) {
-          double a[4];
+      }
+    }
+    __syncthreads();
+    const int m = n - R0;
+    if (m <= 0) break;
+    // A22 -= L21 U12 on the FP64 matrix cores (v_mfma_f64_16x16x4f64: A lane l
+    // -> (row l mod 16, k l / 16), B -> (k l / 16, col l mod 16), D register v
+    // -> (row l / 16 + 4 v, col l mod 16)); L21 from the panel in LDS, U12 and
+    // A22 from the matrix.  Each wavefront takes every fourth 16-row tile row
+    // and sweeps its tile columns four at a time, with all their loads in flight.
+    const int nt = (m + 15) / 16;
+    const int lr = lane & 15, lk = lane >> 4;
+    for (int ti = wv; ti < nt; ti += BS / 64) {
+      double aq[4];
+      const int arow = R0 + 16 * ti + lr;
 #pragma unroll
-          for (int r = 0; r < 4; r++) a[r] = i0 + r < n ? A[(int64_t)(i0 + r) * lda + c] : 0.0;
+      for (int q = 0; q < 4; q++) {
+        const int k = 4 * q + lk;
+        aq[q] = (arow < n && k < kb) ? -pan[(arow - k0) * PS + k] : 0.0;
+      }
+      const int crow = R0 + 16 * ti + lk;
+      for (int tj0 = 0; tj0 < nt; tj0 += 4) {
+        double bq[4][4];
+        v4d acc[4];
 #pragma unroll
-          for (int r = 0; r < 4; r++) {
-            const double *lrow = pan + ((i0 + r < n ? i0 + r : n - 1) - k0) * PS;
-            double acc = a[r];
+        for (int t = 0; t < 4; t++) {
+          const int col = R0 + 16 * (tj0 + t) + lr;
+          const bool cin = (tj0 + t) < nt && col < n;
 #pragma unroll
-            for (int q = 0; q < 16; q++)
-              if (q < kb) acc -= lrow[q] * u[q];
-            a[r] = acc;
+          for (int q = 0; q < 4; q++) {
+            const int k = 4 * q + lk;
+            bq[t][q] = (cin && k < kb) ? A[(int64_t)(k0 + k) * lda + col] : 0.0;
           }
 #pragma unroll
-          for (int r = 0; r < 4; r++)
-            if (i0 + r < n) A[(int64_t)(i0 + r) * lda + c] = a[r];
+          for (int v = 0; v < 4; v++)
+            acc[t][v] = (cin && crow + 4 * v < n) ? A[(int64_t)(crow + 4 * v) * lda + col] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; t++)
+#pragma unroll
+          for (int q = 0; q < 4; q++) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[q], bq[t][q], acc[t], 0, 0, 0);
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          const int col = R0 + 16 * (tj0 + t) + lr;
+          if ((tj0 + t) < nt && col < n) {
+#pragma unroll
+            for (int v = 0; v < 4; v++)
+              if (crow + 4 * v < n) A[(int64_t)(crow + 4 * v) * lda + col] = acc[t][v];
+          }
         }
       }
     }
