@@ -144,6 +144,31 @@ struct Layout {
 
 // ---------------------------------------------------------------- reductions
 
+// Data movement inside a wavefront: DPP within rows of 16 lanes (CTRL 0xB1
+// swaps neighbouring lanes, 0x4E lanes two apart, 0x124 / 0x128 rotate the
+// row by 4 / 8), readlane of one lane for all.
+template <int CTRL>
+__device__ __forceinline__ double dpp_row_mov(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double lane_read(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// Maximum over the wavefront (every lane active), the same bits in every lane.
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp_row_mov<0xB1>(v));
+  v = fmax(v, dpp_row_mov<0x4E>(v));
+  v = fmax(v, dpp_row_mov<0x124>(v));
+  v = fmax(v, dpp_row_mov<0x128>(v));
+  return fmax(fmax(lane_read(v, 0), lane_read(v, 16)), fmax(lane_read(v, 32), lane_read(v, 48)));
+}
+
 template <int BS>
 __device__ inline double block_sum(double v, double *red) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -160,7 +185,7 @@ __device__ inline double block_sum(double v, double *red) {
 template <int BS>
 __device__ inline double block_max(double v, double *red) {
   if (v != v) v = __builtin_inf();
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  v = wave_max(v);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0) red[wid] = v;
@@ -767,6 +792,16 @@ __device__ int lu_factor(T *A, int n, int lda, int *piv, double *red) {
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+// Wavefront argmax for the panel pivot search: the largest v (v >= 0, -1 for
+// rows not in the search) and the first lane index attaining it, for every
+// lane; then a ballot of the lanes equal to the maximum.
+__device__ __forceinline__ void wave_argmax(double v, int vi, double &best, int &bi) {
+  const double m = wave_max(v);
+  const unsigned long long hit = __ballot(v == m);
+  best = m;
+  bi = __builtin_amdgcn_readlane(vi, __builtin_ctzll(hit));
+}
+
 template <int BS>
 __device__ __forceinline__ int lu_factor_mfma32(float *A, int n, int lda, int *piv, double *red, float *pan) {
   static_assert(BS == 256, "one panel row per thread");
@@ -786,11 +821,7 @@ __device__ __forceinline__ int lu_factor_mfma32(float *A, int n, int lda, int *p
       const int k = k0 + jj;
       double v = (tid < rows && tid >= jj) ? fabs((double)pan[tid * PS + jj]) : -1.0;
       int vi = tid;
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(v, off);
-        const int oi = __shfl_xor(vi, off);
-        if (ov > v || (ov == v && oi < vi)) { v = ov; vi = oi; }
-      }
+      wave_argmax(v, tid, v, vi);
       if (lane == 0) { wval[wv] = v; widx[wv] = vi; }
       __syncthreads();
       double best = wval[0];
@@ -930,11 +961,7 @@ __device__ __forceinline__ int lu_factor_blocked64(double *A, int n, int lda, in
       const int k = k0 + jj;
       double v = (tid < rows && tid >= jj) ? fabs(pan[tid * PS + jj]) : -1.0;
       int vi = tid;
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(v, off);
-        const int oi = __shfl_xor(vi, off);
-        if (ov > v || (ov == v && oi < vi)) { v = ov; vi = oi; }
-      }
+      wave_argmax(v, tid, v, vi);
       if (lane == 0) { wval[wv] = v; widx[wv] = vi; }
       __syncthreads();
       double best = wval[0];
