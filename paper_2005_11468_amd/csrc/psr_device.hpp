@@ -160,6 +160,15 @@ __device__ __forceinline__ double lane_read(double v, int l) {
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+// Sum over the wavefront (every lane active) in a fixed order, the same bits
+// in every lane.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_row_mov<0xB1>(v);
+  v += dpp_row_mov<0x4E>(v);
+  v += dpp_row_mov<0x124>(v);
+  v += dpp_row_mov<0x128>(v);
+  return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
+}
 // Maximum over the wavefront (every lane active), the same bits in every lane.
 __device__ __forceinline__ double wave_max(double v) {
   v = fmax(v, dpp_row_mov<0xB1>(v));
@@ -654,6 +663,92 @@ __device__ void jacobian(Ctx &c, const double *x, double *A, int lda) {
   }
   for (int e = tid; e < n * n; e += BS) A[(e / n) * lda + (e % n)] = 0.0;
   __syncthreads();
+  // Row pass by wavefronts: when the reaction scratch (k_f, k_r and the rates
+  // of progress, 4 I doubles, no longer needed) holds a D row and a column
+  // accumulator for each wavefront, wavefront w takes rows w, w + 4, ...:
+  // it gathers D_i. with LDS atomics (lanes over the row's reactions; one
+  // wavefront owns the buffer, so the order of the adds is fixed), applies
+  // the density chain rule and stores row i with lanes over the columns,
+  // adding H_i D_i. to its column accumulator for the energy row.
+  const int nw = BS / 64;
+  if (4 * I >= 2 * N * nw) {
+    const int lane = tid & 63, wv = tid >> 6;
+    double *buf = c.p(c.L.kf) + (size_t)wv * 2 * N;
+    double *col = buf + N;
+    const bool ebal = c.energy == 1;
+    for (int mm = lane; mm < N; mm += 64) col[mm] = 0.0;
+    for (int i = wv; i < N; i += nw) {
+      for (int mm = lane; mm < N; mm += 64) buf[mm] = 0.0;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      double E = 0.0, dT = 0.0;
+      for (int p = m.sp_ptr[i] + lane; p < m.sp_ptr[i + 1]; p += 64) {
+        const int k = m.sp_rx[p];
+        const double nu = m.sp_nu[p];
+        for (int sl = 0; sl < 3; sl++) {
+          const int ir = m.r_idx[3 * k + sl];
+          if (ir >= 0) atomicAdd(&buf[ir], nu * dqdC[6 * k + sl]);
+          const int ip = m.p_idx[3 * k + sl];
+          if (ip >= 0) atomicAdd(&buf[ip], nu * dqdC[6 * k + 3 + sl]);
+        }
+        E += nu * sumC[k];
+        dT += nu * dqdT[k];
+      }
+      E = wave_sum(E);
+      dT = wave_sum(dT);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const double yd = x[i] - Yin[i], Wi = m.W[i], Hi = kR * T * hRT[i];
+      double *row = A + (int64_t)i * lda;
+      for (int mm = lane; mm < N; mm += 64) {
+        const double D = buf[mm];
+        if (ebal) col[mm] += Hi * D;
+        const double SW = S * m.W[mm];
+        double v = -mdot / SW * yd - kV * Wi * (D * rho / m.W[mm] - E / SW);
+        if (mm == i) v += mdot;
+        row[mm] = v;
+      }
+      if (lane == 0) {
+        Erow[i] = E;
+        dwdT[i] = dT;
+        if (c.energy) row[N] = -mdot * invT * yd - kV * Wi * dT;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    __syncthreads();
+    if (c.energy == 2) {  // prescribed temperature: the row V (T - T_in) / tau
+      if (tid == 0) A[(int64_t)N * lda + N] = kV / c.tau;
+      __syncthreads();
+    } else if (c.energy) {
+      double qin = 0.0, dqin = 0.0, tt = 0.0, hE = 0.0;
+      for (int i = tid; i < N; i += BS) {
+        const double H = kR * T * hRT[i];
+        qin += Yin[i] * (H - Hin[i]) / m.W[i];
+        dqin += Yin[i] * kR * cpR[i] / m.W[i];
+        tt += kV * (kR * cpR[i] * wdot[i] + H * dwdT[i]);
+        hE += H * Erow[i];
+      }
+      const double Qin = block_sum<BS>(qin, red);
+      const double dQin = block_sum<BS>(dqin, red);
+      const double TT = block_sum<BS>(tt, red);
+      const double HE = block_sum<BS>(hE, red);
+      const double *col0 = c.p(c.L.kf) + N;
+      for (int mm = tid; mm < N; mm += BS) {
+        double v = 0.0;
+        for (int w = 0; w < nw; w++) v += col0[(size_t)w * 2 * N + mm];
+        const double SW = S * m.W[mm];
+        A[(int64_t)N * lda + mm] = -mdot * Qin / SW + kV * (v * rho / m.W[mm] - HE / SW);
+      }
+      if (tid == 0) A[(int64_t)N * lda + N] = -mdot * invT * Qin + mdot * dQin + TT;
+      __syncthreads();
+    }
+    if (c.energy && m.soot) soot_jacobian<BS>(c, x, A, lda);
+    return;
+  }
   // gather D (into the species rows of A), E_i = sum_j D_ij C_j, dwdot_i/dT
   for (int i = tid; i < N; i += BS) {
     double E = 0.0, dT = 0.0;
