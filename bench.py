@@ -308,14 +308,16 @@ def timed_solves(P, groups, x0s, opts, steps, warmup, ws=None):
 
 def oracle_parity(O, mech, cond, energy, idx, x, status, xo, so, tol, opts=None):
     """Per-reactor parity of GPU results on the oracle sample idx (the same
-    reading as the tests): agree within tol; branch mismatch or GPU-only root
-    verified by an oracle restart at the GPU root: it converges, either with
-    its first linear solve (the oracle's own convergence test accepts the
-    GPU root; trace species may then differ by up to the step-norm weight
-    atol_Y + rtol |Y|) or to within tol of the GPU root; oracle-only roots
-    counted as misses.  Returns
-    counts and the fraction of the GPU-converged sample reactors that are
-    verified steady states."""
+    reading as the tests): agree within tol; a GPU-only root within tol of
+    the oracle's last iterate is the same state (the oracle reached it but
+    its convergence test failed by rounding); any other branch mismatch or
+    GPU-only root is verified by an oracle restart at the GPU root: it
+    converges, either with its first linear solve (the oracle's own
+    convergence test accepts the GPU root; trace species may then differ by
+    up to the step-norm weight atol_Y + rtol |Y|) or to within tol of the GPU
+    root; oracle-only roots counted as misses.  Returns counts and the
+    fraction of the GPU-converged sample reactors that are verified steady
+    states."""
     from tests.gpu_util import rel_err
     n_sp = mech["species_elems"].shape[0]
     xg, sg = x[:, idx], status[idx]
@@ -325,9 +327,12 @@ def oracle_parity(O, mech, cond, energy, idx, x, status, xo, so, tol, opts=None)
     agree = both & (err <= tol)
     om = O.Mechanism(mech)
     opts = O.default_opts(**(opts or {}))
-    verified, unverified = 0, 0
+    verified, unverified, same_state = 0, 0, 0
     for j in np.flatnonzero(conv_g & ~agree):
         b = int(idx[j])
+        if not conv_o[j] and err[j] <= tol:
+            same_state += 1
+            continue
         args = (cond["P"][b], cond["tau"][b], cond["T_in"][b], cond["Y_in"][:, b], energy)
         xr, st = om.solve(*args, xg[:, j], opts)
         e = rel_err(xg[:, j:j + 1], xr[:, None], n_sp)[0]
@@ -342,8 +347,9 @@ def oracle_parity(O, mech, cond, energy, idx, x, status, xo, so, tol, opts=None)
             "agree": int(agree.sum()), "max_rel_err": float(err[agree].max()) if agree.any() else None,
             "branch_mismatch": int((both & ~agree).sum()), "gpu_only": int((conv_g & ~conv_o).sum()),
             "verified_other_roots": verified, "unverified": unverified,
+            "gpu_only_at_oracle_state": same_state,
             "oracle_only": int((conv_o & ~conv_g).sum()),
-            "valid_fraction": (int(agree.sum()) + verified) / ng if ng else 0.0}
+            "valid_fraction": (int(agree.sum()) + verified + same_state) / ng if ng else 0.0}
 
 
 def cpu_cores():

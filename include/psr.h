@@ -291,6 +291,14 @@ typedef struct {
    * reaches them.  Other multi-group persistent calls launch one kernel per
    * group, side by side.  Both give the same bits per reactor. */
   int32_t order;
+  /* mixed precision: the largest system size n factored in FP32 first
+   * (default 64, the wavefront engine's range).  Larger systems are factored
+   * in FP64 directly: after equilibration their Jacobians (100 to 201
+   * unknowns here) reach condition numbers near 1e13, 78-80 % of the float
+   * attempts fall back to FP64, and the float attempt plus its refinement
+   * costs more than it saves.  Such factorisations are not counted as
+   * fallbacks in psr_solve_stats. */
+  int32_t mixed_max_n;
 } psr_solve_opts;
 
 /* Fill opts with the defaults (FP64, plain scheduler, graph replay on,

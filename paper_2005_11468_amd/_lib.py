@@ -51,7 +51,7 @@ class SolveOpts(C.Structure):
                 ("rpw", C.c_int32), ("grid_per_cu", C.c_int32),
                 ("lnM_step", C.c_double), ("ct_ratio", C.c_double),
                 ("ct_tau_min", C.c_double), ("ct_min_step", C.c_double),
-                ("order", C.c_int32)]
+                ("order", C.c_int32), ("mixed_max_n", C.c_int32)]
 
 
 class Group(C.Structure):

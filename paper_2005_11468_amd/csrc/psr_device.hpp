@@ -59,6 +59,7 @@ struct Opts {
   double atol_lnM, ts_atol_lnM;  // soot moments
   double lnM_step;               // largest |d ln M_r| of one Newton step
   double ct_ratio, ct_tau_min, ct_min_step;  // continuation in tau
+  int mixed_max_n;  // mixed precision: largest system factored in FP32 first
 };
 
 // Mixed precision: refinement target of the solve whose Newton step ends a

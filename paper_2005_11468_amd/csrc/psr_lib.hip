@@ -651,6 +651,7 @@ extern "C" void psr_default_opts(psr_solve_opts *o) {
   o->ct_tau_min = 1e-6;
   o->ct_min_step = 0.05;
   o->order = 1;
+  o->mixed_max_n = 64;
 }
 
 // Lagrange basis polynomial l over the nodes 0..m-1, at p.
@@ -1214,6 +1215,7 @@ static Opts to_dev_opts(const psr_solve_opts *o) {
   d.atol_lnM = o->atol_lnM; d.ts_atol_lnM = o->ts_atol_lnM;
   d.lnM_step = o->lnM_step;
   d.ct_ratio = o->ct_ratio; d.ct_tau_min = o->ct_tau_min; d.ct_min_step = o->ct_min_step;
+  d.mixed_max_n = o->mixed_max_n;
   return d;
 }
 
@@ -1489,7 +1491,7 @@ static psr_status check_opts(const psr_solve_opts *o) {
       !(o->ts_atol_lnM >= 0) || !(o->rpw == 0 || o->rpw == 1 || o->rpw == 2 || o->rpw == 4) ||
       o->grid_per_cu < 0 || o->grid_per_cu > 32 || !(o->lnM_step > 0) ||
       !(o->ct_ratio >= 0) || !(o->ct_tau_min > 0) || !(o->ct_min_step > 0) || o->order < 0 ||
-      o->order > 1)
+      o->order > 1 || o->mixed_max_n < 0)
     return fail(PSR_EINVAL, "option out of range");
   return PSR_OK;
 }

@@ -366,7 +366,10 @@ __device__ void round_step(Ctx &c, const Opts &o, RState &s) {
     s.fin = all_finite<BS>(G, n, red) && matrix_finite<BS>(A64, n, lda, red);
     s.sing = 0;
     if (s.fin) {
-      if (MIXED && s.stick > 0) {  // recent fallback: FP64 directly
+      if (MIXED && n > o.mixed_max_n) {  // above the float size limit: FP64 only
+        s.fb64 = 1;
+        want64 = true;
+      } else if (MIXED && s.stick > 0) {  // recent fallback: FP64 directly
         s.stick--;
         s.fb64 = 1;
         s.n_fb64++;

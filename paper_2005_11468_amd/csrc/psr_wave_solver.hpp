@@ -321,12 +321,13 @@ __device__ __forceinline__ void w_round(const WCtx &c, const WArea<NP> &A, const
       if (MIXED) {
         // after a recent fallback the float attempt is skipped (one call
         // site of each factorisation either way)
-        const bool direct = s.stick > 0;
+        const bool big = c.n > o.mixed_max_n;  // above the float size limit: FP64 only
+        const bool direct = !big && s.stick > 0;
         if (direct) s.stick--;
-        if (direct || factor32<NP, MIXED>(c, A, r) != 0) {
+        if (big || direct || factor32<NP, MIXED>(c, A, r) != 0) {
           s.fb64 = 1;
-          s.n_fb64++;
-          if (!direct) note_fallback(s);
+          if (!big) s.n_fb64++;
+          if (!big && !direct) note_fallback(s);
           s.sing = factor64<NP, MIXED>(c, A, r) != 0;
         }
       } else {
