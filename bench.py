@@ -244,8 +244,9 @@ def newton_sweep(P, sizes, steps=3, fd_max=100_000):
 def lu_large(P, n=201, B=9830, steps=3):
     """psr_lu_factor_batch with float factors on B seeded random n x n
     matrices (the 200/1200 mechanism's matrix size and reactor count of the
-    uneven workload): blocked LU with matrix-core trailing updates; each
-    timed launch factors a fresh copy (the copy is outside the events)."""
+    uneven workload): one wavefront per matrix, register panel, trailing
+    updates on the FP32 matrix cores; each timed launch factors a fresh copy
+    (the copy is outside the events)."""
     import torch
     g = torch.Generator(device="cuda:0")
     g.manual_seed(2011)
@@ -274,7 +275,7 @@ def lu_large(P, n=201, B=9830, steps=3):
     tf = flops / (ms / 1e3) / 1e12
     ok = int((info == 0).sum().item())
     del A0, A
-    return {"kernel": "k_lu_factor_big", "n": n, "matrices": B, "ms_per_launch": ms,
+    return {"kernel": "k_lu_factor_wave", "n": n, "matrices": B, "ms_per_launch": ms,
             "alg_flops": flops, "achieved_tflops": tf, "peak_tflops": PEAK_MFMA_F32_TFLOPS,
             "frac_mfma_f32": tf / PEAK_MFMA_F32_TFLOPS, "nonsingular": ok}
 

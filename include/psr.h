@@ -193,7 +193,8 @@ psr_status psr_jacobian_fd_noalloc(psr_mech_t mech, const psr_conditions *cond, 
 /* Batched LU with partial pivoting of B independent n x n row-major
  * matrices (device [B][n][n], overwritten by L\U with unit-lower L), pivots
  * device [B][n] (LAPACK convention: row k was swapped with row piv[k]),
- * info device [B] (0, or k+1 if column k had no nonzero pivot).
+ * info device [B] (0, or k+1 if column k had no nonzero pivot; the
+ * factors and pivots from column k on are then unspecified).
  * precision PSR_FP64 factors in double; PSR_MIXED rounds each matrix to
  * float, factors in float and writes the float factors back as double.
  * Asynchronous.  For PSR_MIXED with 64 < n <= 256 the factorisation works

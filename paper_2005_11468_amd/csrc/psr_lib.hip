@@ -23,7 +23,7 @@
 #include <vector>
 
 #include "../../include/psr.h"
-#include "psr_lu_lds.hpp"
+#include "psr_lu_wave.hpp"
 #include "psr_solver.hpp"
 #include "psr_wave_solver.hpp"
 
@@ -144,49 +144,20 @@ __global__ void __launch_bounds__(kBS) k_lu_factor(int n, double *A, int *piv, i
   if (threadIdx.x == 0) info[b] = r;
 }
 
-// Float factors of large matrices (64 < n <= 256): grid-stride over the
-// batch, each workgroup factoring in its own float scratch area in HBM with
-// the blocked matrix-core LU.
-__global__ void __launch_bounds__(kBS) k_lu_factor_big(int n, int64_t batch, double *A, int *piv, int *info,
-                                                       float *scratch) {
-  __shared__ double red[kBS + 8];
-  __shared__ float pan[256 * 17];
-  const int lda = n;
-  float *M = scratch + (int64_t)blockIdx.x * n * n;
-  for (int64_t b = blockIdx.x; b < batch; b += gridDim.x) {
-    double *g = A + b * (int64_t)n * n;
-    for (int e = threadIdx.x; e < n * n; e += kBS) M[e] = (float)g[e];
-    __syncthreads();
-    const int r = lu_factor_mfma32<kBS>(M, n, lda, piv + b * n, red, pan);
-    __syncthreads();
-    for (int e = threadIdx.x; e < n * n; e += kBS) g[e] = (double)M[e];
-    if (r != 0)
-      for (int k = r - 1 + threadIdx.x; k < n; k += kBS) piv[b * n + k] = k;
-    if (threadIdx.x == 0) info[b] = r;
-    __syncthreads();
-  }
-}
-
-// Float factors of large matrices whose float copy fits one workgroup's LDS
-// (64 < n <= 201 on gfx950): grid-stride over the batch, one workgroup of
-// kLuNT threads per CU, the whole matrix resident in LDS.
-constexpr int kLuNT = 256;
-__global__ void __launch_bounds__(kLuNT) k_lu_factor_lds(int n, int64_t batch, double *A, int *piv, int *info) {
+// Float factors of large matrices (64 < n <= 256), one wavefront per matrix:
+// four independent wavefronts per workgroup, each with its own LDS panel
+// area and its own padded float working area in HBM.
+__global__ void __launch_bounds__(256) k_lu_factor_wave(int n, int ld, int64_t batch, double *A, int *piv,
+                                                        int *info, float *scratch) {
   extern __shared__ double lds[];
-  const int lda = (n % 2 == 0) ? n + 1 : n;
-  float *M = reinterpret_cast<float *>(lds);
-  int *pv = reinterpret_cast<int *>(M + n * lda);
-  int *s_info = pv + n;
-  for (int64_t b = blockIdx.x; b < batch; b += gridDim.x) {
-    double *g = A + b * (int64_t)n * n;
-    psr::lulds::load_f32<kLuNT>(M, n, lda, g);
-    __syncthreads();
-    const int r = psr::lulds::factor<kLuNT>(M, n, lda, pv, s_info);
-    __syncthreads();
-    psr::lulds::store_f64<kLuNT>(M, n, lda, g);
-    for (int k = threadIdx.x; k < n; k += kLuNT) piv[b * n + k] = (r == 0 || k < r - 1) ? pv[k] : k;
-    if (threadIdx.x == 0) info[b] = r;
-    __syncthreads();
+  psr::luw::WaveLds *sh = reinterpret_cast<psr::luw::WaveLds *>(lds);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t worker = (int64_t)blockIdx.x * psr::luw::kW + wv;
+  const int64_t nworkers = (int64_t)gridDim.x * psr::luw::kW;
+  float *M = scratch + worker * (int64_t)psr::luw::pad_rows(n) * ld;
+  for (int64_t b = worker; b < batch; b += nworkers) {
+    const int r = psr::luw::factor(n, ld, A + b * (int64_t)n * n, M, piv + b * n, sh[wv], lane);
+    if (lane == 0) info[b] = r;
   }
 }
 
@@ -1144,34 +1115,23 @@ extern "C" psr_status psr_lu_factor_batch(int32_t n, int64_t batch, int32_t prec
   if (batch > 0x7fffffffLL) return fail(PSR_EUNSUPPORTED, "batch above 2^31-1");
   const int lda = (n % 2 == 0) ? n + 1 : n;
   const bool f32 = precision == PSR_MIXED;
-  const size_t lds_res = (size_t)n * lda * 4 + (size_t)n * 4 + 16;
-  int per_cu = 0;
-  if (f32 && n > 64 && n <= kLuNT && lds_res <= (size_t)lds_limit_bytes())
-    HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_lu_factor_lds, kLuNT, lds_res));
-  if (per_cu >= 2) {
-    // the whole float matrix in LDS, as many workgroups per CU as fit: with
-    // one per CU (n above ~140) the latency of the sequential panel steps is
-    // not hidden and the HBM-scratch kernel below, two per CU, is faster
-    int dev = 0, ncu = 0;
-    HIP_OK(hipGetDevice(&dev));
-    HIP_OK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    const int64_t grid = std::min<int64_t>(batch, (int64_t)ncu * per_cu);
-    hipLaunchKernelGGL(k_lu_factor_lds, dim3((unsigned)grid), dim3(kLuNT), lds_res, (hipStream_t)stream, n, batch,
-                       A, piv, info);
-    HIP_OK(hipGetLastError());
-    return PSR_OK;
-  }
   if (f32 && n > 64 && n <= 256) {
-    // blocked matrix-core LU, one float scratch matrix per resident workgroup
-    int dev = 0, ncu = 0;
+    // one wavefront per matrix, float working copies in a library-owned area
+    int dev = 0, ncu = 0, per_cu = 0;
+    const size_t lds = sizeof(psr::luw::WaveLds) * psr::luw::kW;
     HIP_OK(hipGetDevice(&dev));
     HIP_OK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    const int64_t grid = std::min<int64_t>(batch, (int64_t)ncu * 2);
-    float *panel_ws = nullptr;
-    const psr_status st = lu_scratch(dev, (hipStream_t)stream, (size_t)grid * n * n * sizeof(float), &panel_ws);
+    HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_lu_factor_wave, 256, lds));
+    if (per_cu < 1) return fail(PSR_EUNSUPPORTED, "LU kernel does not fit a compute unit");
+    const int ldw = psr::luw::pad_ld(n);
+    const int64_t grid = std::min<int64_t>((batch + psr::luw::kW - 1) / psr::luw::kW, (int64_t)ncu * per_cu);
+    float *work = nullptr;
+    const psr_status st = lu_scratch(dev, (hipStream_t)stream,
+                                     (size_t)grid * psr::luw::kW * psr::luw::pad_rows(n) * ldw * sizeof(float),
+                                     &work);
     if (st != PSR_OK) return st;
-    hipLaunchKernelGGL(k_lu_factor_big, dim3((unsigned)grid), dim3(kBS), 0, (hipStream_t)stream, n, batch, A,
-                       piv, info, panel_ws);
+    hipLaunchKernelGGL(k_lu_factor_wave, dim3((unsigned)grid), dim3(256), lds, (hipStream_t)stream, n, ldw, batch,
+                       A, piv, info, work);
     HIP_OK(hipGetLastError());
     return PSR_OK;
   }

@@ -129,16 +129,16 @@ def test_lu_float_factors_backward_error(gpu, n):
         assert err <= 4 * n * np.finfo(np.float32).eps
 
 
-@pytest.mark.parametrize("n,B", [(65, 7), (101, 520), (128, 600), (143, 40), (201, 9), (256, 3)])
+@pytest.mark.parametrize("n,B", [(65, 7), (101, 1300), (128, 600), (143, 40), (201, 9), (256, 3)])
 def test_lu_float_blocked_matrix_core(gpu, n, B):
-    """Float factors for 64 < n <= 256 come from the blocked LU with
-    matrix-core trailing updates (panel width 16): LDS-resident while two
-    matrices fit one CU's LDS (n up to about 140), HBM scratch above.  Random matrices without a
-    dominant diagonal, so rows are really interchanged.  Checked by the
-    properties partial pivoting guarantees: |L| <= 1 and a backward error
-    |P A - L U| within a small multiple of n eps_float |L| |U|.  B = 520
-    exceeds the number of resident workgroups, so the grid-stride loop is
-    exercised."""
+    """Float factors for 64 < n <= 256 come from the blocked LU with one
+    wavefront per matrix (16-column panel in registers, trailing updates on
+    the matrix cores, row interchanges as a row map).  Random matrices
+    without a dominant diagonal, so rows are really interchanged.  Checked
+    by the properties partial pivoting guarantees: |L| <= 1 and a backward
+    error |P A - L U| within a small multiple of n eps_float |L| |U|.  B =
+    1300 exceeds the 1024 wavefronts resident on the chip, so each
+    wavefront's loop over matrices runs more than once."""
     rng = np.random.default_rng(900 + n)
     A = rng.standard_normal((B, n, n))
     LU, piv, info = gpu.lu_factor_batch(dev(A.copy()), precision=gpu.PSR_MIXED)
