@@ -249,11 +249,11 @@ __device__ __forceinline__ void panel_step(int n, int ld, int k0, double *g, flo
   lds_order();
   const int m = n - R0;
   if (m <= 0) return;
-  // ---- U12 = L11^-1 A12, columns R0 + lane + 64 g
+  // ---- U12 = L11^-1 A12, columns R0 + lane + 64 g (m > 0, so kb = 16)
   float u[4][16];
   int prow[16];
 #pragma unroll
-  for (int i = 0; i < 16; i++) prow[i] = S.perm[k0 + (i < kb ? i : 0)];
+  for (int i = 0; i < 16; i++) prow[i] = S.perm[k0 + i];
 #pragma unroll
   for (int gq = 0; gq < 4; gq++) {
     const int c = R0 + lane + 64 * gq;
@@ -261,18 +261,20 @@ __device__ __forceinline__ void panel_step(int n, int ld, int k0, double *g, flo
 #pragma unroll
     for (int i = 0; i < 16; i++) {
       const float v = ld_elem<FIRST>(g, M, n, ld, prow[i], cc);
-      u[gq][i] = (i < kb && c < n) ? v : 0.f;
+      u[gq][i] = c < n ? v : 0.f;
     }
   }
+  // L11 row l in lane l (l < 16); its elements reach every lane by readlane
+  float lrow[16];
+#pragma unroll
+  for (int t = 0; t < 16; t++) lrow[t] = S.L[(lane & 15) * kPS + t];
 #pragma unroll
   for (int i = 1; i < 16; i++) {
 #pragma unroll
-    for (int t = 0; t < 16; t++) {
-      if (t < i && i < kb) {
-        const float lit = S.L[i * kPS + t];
+    for (int t = 0; t < i; t++) {
+      const float lit = rdlane(lrow[t], i);
 #pragma unroll
-        for (int gq = 0; gq < 4; gq++) u[gq][i] = fmaf(-lit, u[gq][t], u[gq][i]);
-      }
+      for (int gq = 0; gq < 4; gq++) u[gq][i] = fmaf(-lit, u[gq][t], u[gq][i]);
     }
   }
 #pragma unroll
@@ -280,8 +282,8 @@ __device__ __forceinline__ void panel_step(int n, int ld, int k0, double *g, flo
     const int c = R0 + lane + 64 * gq;
 #pragma unroll
     for (int i = 0; i < 16; i++) {
-      if (c < n && i < kb) M[(int64_t)prow[i] * ld + c] = u[gq][i];
-      S.U[i * kUS + lane + 64 * gq] = u[gq][i];  // zero outside the block
+      if (c < ld) M[(int64_t)prow[i] * ld + c] = u[gq][i];  // columns past n: padding
+      S.U[i * kUS + lane + 64 * gq] = u[gq][i];           // zero past n
     }
   }
   lds_order();
