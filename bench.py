@@ -440,6 +440,14 @@ def soot(P, steps=1, warmup=1, sample=32, cores=16):
     out = {"reactors": B, "n": int(x0.shape[0]), "converged": int(st.converged), "ms_per_solve": ms,
            "ms_all": times, "kernel_ms": st.kernel_ms, "lin_total": int(st.lin_total),
            "jac_total": int(st.jac_total), "fp64_fallbacks": int(st.fp64_fallbacks)}
+    # the workgroup engine's own roofline line: the same per-unit counts as
+    # the headline (LU + Jacobian per linearisation, residual + solve per
+    # round), over the persistent kernel's duration
+    N, I, n = mech["species_elems"].shape[0], mech["A"].shape[0], int(x0.shape[0])
+    fl = st.jac_total * (lu_flops(n) + jacobian_flops(n, I)) + st.lin_total * (residual_flops(N, I) + solve_flops(n))
+    tf = fl / (st.kernel_ms / 1e3) / 1e12
+    out["roofline"] = {"kernel": "k_persistent<true,true>", "bound": "alu", "alg_flops": fl, "achieved": tf,
+                       "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": tf / PEAK_ALU_TFLOPS}
     valid = float(st.converged)
     if sample > 0:
         from oracle import oracle as O
