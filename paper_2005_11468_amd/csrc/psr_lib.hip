@@ -144,19 +144,20 @@ __global__ void __launch_bounds__(kBS) k_lu_factor(int n, double *A, int *piv, i
   if (threadIdx.x == 0) info[b] = r;
 }
 
-// Float factors of large matrices (64 < n <= 256), one wavefront per matrix:
-// four independent wavefronts per workgroup, each with its own LDS panel
-// area and its own padded float working area in HBM.
+// Factors of large matrices (float 64 < n <= 256, FP64 64 < n <= 128), one
+// wavefront per matrix: four independent wavefronts per workgroup, each with
+// its own LDS panel area and its own padded working area in HBM.
+template <typename T>
 __global__ void __launch_bounds__(256) k_lu_factor_wave(int n, int ld, int64_t batch, double *A, int *piv,
-                                                        int *info, float *scratch) {
+                                                        int *info, T *scratch) {
   extern __shared__ double lds[];
-  psr::luw::WaveLds *sh = reinterpret_cast<psr::luw::WaveLds *>(lds);
+  psr::luw::WaveLds<T> *sh = reinterpret_cast<psr::luw::WaveLds<T> *>(lds);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t worker = (int64_t)blockIdx.x * psr::luw::kW + wv;
   const int64_t nworkers = (int64_t)gridDim.x * psr::luw::kW;
-  float *M = scratch + worker * (int64_t)psr::luw::pad_rows(n) * ld;
+  T *M = scratch + worker * (int64_t)psr::luw::pad_rows(n) * ld;
   for (int64_t b = worker; b < batch; b += nworkers) {
-    const int r = psr::luw::factor(n, ld, A + b * (int64_t)n * n, M, piv + b * n, sh[wv], lane);
+    const int r = psr::luw::factor<T>(n, ld, A + b * (int64_t)n * n, M, piv + b * n, sh[wv], lane);
     if (lane == 0) info[b] = r;
   }
 }
@@ -1109,32 +1110,37 @@ static psr_status lu_scratch(int dev, hipStream_t stream, size_t bytes, float **
   return PSR_OK;
 }
 
+// One wavefront per matrix, working copies in a library-owned area per
+// (device, stream).
+template <typename T>
+static psr_status lu_factor_wave(int n, int64_t batch, double *A, int *piv, int *info, hipStream_t stream) {
+  int dev = 0, ncu = 0, per_cu = 0;
+  const size_t lds = sizeof(psr::luw::WaveLds<T>) * psr::luw::kW;
+  HIP_OK(hipGetDevice(&dev));
+  HIP_OK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_lu_factor_wave<T>, 256, lds));
+  if (per_cu < 1) return fail(PSR_EUNSUPPORTED, "LU kernel does not fit a compute unit");
+  const int ldw = psr::luw::pad_ld(n);
+  const int64_t grid = std::min<int64_t>((batch + psr::luw::kW - 1) / psr::luw::kW, (int64_t)ncu * per_cu);
+  float *work = nullptr;
+  const psr_status st =
+      lu_scratch(dev, stream, (size_t)grid * psr::luw::kW * psr::luw::pad_rows(n) * ldw * sizeof(T), &work);
+  if (st != PSR_OK) return st;
+  hipLaunchKernelGGL(k_lu_factor_wave<T>, dim3((unsigned)grid), dim3(256), lds, stream, n, ldw, batch, A, piv, info,
+                     reinterpret_cast<T *>(work));
+  HIP_OK(hipGetLastError());
+  return PSR_OK;
+}
+
 extern "C" psr_status psr_lu_factor_batch(int32_t n, int64_t batch, int32_t precision, double *A,
                                           int32_t *piv, int32_t *info, void *stream) {
   if (n <= 0 || batch <= 0 || !A || !piv || !info) return fail(PSR_EINVAL, "bad LU arguments");
   if (batch > 0x7fffffffLL) return fail(PSR_EUNSUPPORTED, "batch above 2^31-1");
   const int lda = (n % 2 == 0) ? n + 1 : n;
   const bool f32 = precision == PSR_MIXED;
-  if (f32 && n > 64 && n <= 256) {
-    // one wavefront per matrix, float working copies in a library-owned area
-    int dev = 0, ncu = 0, per_cu = 0;
-    const size_t lds = sizeof(psr::luw::WaveLds) * psr::luw::kW;
-    HIP_OK(hipGetDevice(&dev));
-    HIP_OK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_lu_factor_wave, 256, lds));
-    if (per_cu < 1) return fail(PSR_EUNSUPPORTED, "LU kernel does not fit a compute unit");
-    const int ldw = psr::luw::pad_ld(n);
-    const int64_t grid = std::min<int64_t>((batch + psr::luw::kW - 1) / psr::luw::kW, (int64_t)ncu * per_cu);
-    float *work = nullptr;
-    const psr_status st = lu_scratch(dev, (hipStream_t)stream,
-                                     (size_t)grid * psr::luw::kW * psr::luw::pad_rows(n) * ldw * sizeof(float),
-                                     &work);
-    if (st != PSR_OK) return st;
-    hipLaunchKernelGGL(k_lu_factor_wave, dim3((unsigned)grid), dim3(256), lds, (hipStream_t)stream, n, ldw, batch,
-                       A, piv, info, work);
-    HIP_OK(hipGetLastError());
-    return PSR_OK;
-  }
+  if (n > 64 && n <= (f32 ? psr::luw::Prec<float>::NMAX : psr::luw::Prec<double>::NMAX))
+    return f32 ? lu_factor_wave<float>(n, batch, A, piv, info, (hipStream_t)stream)
+               : lu_factor_wave<double>(n, batch, A, piv, info, (hipStream_t)stream);
   const size_t lds = ((size_t)n * lda * (f32 ? 4 : 8) + 7) / 8 * 8 + (kBS + 8) * 8 + (size_t)n * 4 + 8;
   if (lds > (size_t)lds_limit_bytes()) return fail(PSR_EUNSUPPORTED, "matrix too large for LDS");
   if (f32)
