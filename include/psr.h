@@ -197,8 +197,9 @@ psr_status psr_jacobian_fd_noalloc(psr_mech_t mech, const psr_conditions *cond, 
  * factors and pivots from column k on are then unspecified).
  * precision PSR_FP64 factors in double; PSR_MIXED rounds each matrix to
  * float, factors in float and writes the float factors back as double.
- * Asynchronous.  For PSR_MIXED with 64 < n <= 256 the factorisation works
- * in a library-owned device buffer, one per (device, stream) pair, allocated
+ * Asynchronous.  For PSR_MIXED with 64 < n <= 256 and PSR_FP64 with
+ * 64 < n <= 128 the factorisation works (one wavefront per matrix) in a
+ * library-owned device buffer, one per (device, stream) pair, allocated
  * on the first such call and grown on demand (that call synchronises the
  * stream before freeing the smaller buffer); calls on one stream are ordered
  * and calls on different streams use different buffers, so concurrent calls

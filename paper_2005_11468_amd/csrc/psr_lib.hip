@@ -162,6 +162,104 @@ __global__ void __launch_bounds__(256) k_lu_factor_wave(int n, int ld, int64_t b
   }
 }
 
+// Triangular solves with the factors of n <= 256 matrices, one wavefront per
+// matrix: the right-hand side in registers (element i in lane i mod 64, slot
+// i / 64), the interchanges applied in order, then row-oriented forward and
+// back substitution -- each row of L and U read once, coalesced, the next
+// row's loads issued before the current row's wavefront sum.
+__global__ void __launch_bounds__(256) k_lu_solve_wave(int n, int64_t batch, const double *LU, const int *piv,
+                                                       double *rhs) {
+  constexpr int NS = 4;
+  const int lane = threadIdx.x & 63;
+  const int64_t worker = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t nworkers = (int64_t)gridDim.x * 4;
+  for (int64_t b = worker; b < batch; b += nworkers) {
+    const double *A = LU + b * (int64_t)n * n;
+    const int *pv = piv + b * n;
+    double *r = rhs + b * n;
+    double z[NS];
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+      const int i = lane + 64 * s;
+      z[s] = i < n ? r[i] : 0.0;
+    }
+    for (int k = 0; k < n; k++) {
+      const int p = pv[k];
+      if (p == k) continue;
+      double zk = 0.0, zp = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; s++) {
+        if (s == (k >> 6)) zk = lane_read(z[s], k & 63);
+        if (s == (p >> 6)) zp = lane_read(z[s], p & 63);
+      }
+#pragma unroll
+      for (int s = 0; s < NS; s++) {
+        const int i = lane + 64 * s;
+        z[s] = i == k ? zp : (i == p ? zk : z[s]);
+      }
+    }
+    // forward: z_i -= sum_{k < i} L_ik z_k (unit diagonal)
+    double cur[NS], nxt[NS];
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+      const int c = lane + 64 * s;
+      cur[s] = (n > 1 && c < n) ? A[(int64_t)1 * n + c] : 0.0;
+    }
+    for (int i = 1; i < n; i++) {
+      if (i + 1 < n) {
+#pragma unroll
+        for (int s = 0; s < NS; s++) {
+          const int c = lane + 64 * s;
+          nxt[s] = c < n ? A[(int64_t)(i + 1) * n + c] : 0.0;
+        }
+      }
+      double d = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; s++) {
+        const int c = lane + 64 * s;
+        d = c < i ? fma(cur[s], z[s], d) : d;
+      }
+      d = wave_sum(d);
+#pragma unroll
+      for (int s = 0; s < NS; s++) z[s] = (lane + 64 * s) == i ? z[s] - d : z[s];
+#pragma unroll
+      for (int s = 0; s < NS; s++) cur[s] = nxt[s];
+    }
+    // back: z_i = (z_i - sum_{k > i} U_ik z_k) / U_ii
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+      const int c = lane + 64 * s;
+      cur[s] = c < n ? A[(int64_t)(n - 1) * n + c] : 0.0;
+    }
+    for (int i = n - 1; i >= 0; i--) {
+      if (i > 0) {
+#pragma unroll
+        for (int s = 0; s < NS; s++) {
+          const int c = lane + 64 * s;
+          nxt[s] = c < n ? A[(int64_t)(i - 1) * n + c] : 0.0;
+        }
+      }
+      double d = 0.0, uii = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; s++) {
+        const int c = lane + 64 * s;
+        d = (c > i && c < n) ? fma(cur[s], z[s], d) : d;
+        if (s == (i >> 6)) uii = lane_read(cur[s], i & 63);
+      }
+      d = wave_sum(d);
+#pragma unroll
+      for (int s = 0; s < NS; s++) z[s] = (lane + 64 * s) == i ? (z[s] - d) / uii : z[s];
+#pragma unroll
+      for (int s = 0; s < NS; s++) cur[s] = nxt[s];
+    }
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+      const int i = lane + 64 * s;
+      if (i < n) r[i] = z[s];
+    }
+  }
+}
+
 __global__ void __launch_bounds__(kBS) k_lu_solve(int n, const double *A, const int *piv, double *rhs) {
   extern __shared__ double lds[];
   const int64_t b = blockIdx.x;
@@ -1158,6 +1256,16 @@ extern "C" psr_status psr_lu_solve_batch(int32_t n, int64_t batch, const double 
   if (n <= 0 || batch <= 0 || !LU || !piv || !b) return fail(PSR_EINVAL, "bad LU arguments");
   if (batch > 0x7fffffffLL) return fail(PSR_EUNSUPPORTED, "batch above 2^31-1");
   const int lda = (n % 2 == 0) ? n + 1 : n;
+  if (n <= 256) {
+    int dev = 0, ncu = 0;
+    HIP_OK(hipGetDevice(&dev));
+    HIP_OK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int64_t grid = std::min<int64_t>((batch + 3) / 4, (int64_t)ncu * 8);
+    hipLaunchKernelGGL(k_lu_solve_wave, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream, n, batch, LU, piv,
+                       b);
+    HIP_OK(hipGetLastError());
+    return PSR_OK;
+  }
   const size_t lds = (size_t)n * lda * 8 + (size_t)n * 8 + (size_t)n * 4 + 8;
   if (lds > (size_t)lds_limit_bytes()) return fail(PSR_EUNSUPPORTED, "matrix too large for LDS");
   hipLaunchKernelGGL(k_lu_solve, dim3((unsigned)batch), dim3(kBS), lds, (hipStream_t)stream, n, LU, piv,

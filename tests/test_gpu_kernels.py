@@ -82,7 +82,7 @@ def test_jacobian_matches_oracle(gpu, oracle_mod, case):
         assert not bad.any(), (name, b, np.argwhere(bad)[:4])
 
 
-@pytest.mark.parametrize("n", [1, 3, 17, 54, 64, 65, 101])
+@pytest.mark.parametrize("n", [1, 3, 17, 54, 64, 65, 101, 128])
 def test_lu_fp64_matches_oracle(gpu, oracle_mod, n):
     rng = np.random.default_rng(300 + n)
     B = 13
@@ -99,6 +99,35 @@ def test_lu_fp64_matches_oracle(gpu, oracle_mod, n):
     for b in range(B):
         zo = oracle_mod.lu_solve(LU[b], piv[b], rhs[b])
         np.testing.assert_allclose(z[b], zo, rtol=1e-9, atol=1e-12 * np.abs(zo).max())
+
+
+def test_lu_fp64_wavefront_kernel_many_matrices(gpu, oracle_mod):
+    """FP64 factors for 64 < n <= 128 come from the one-wavefront-per-matrix
+    kernel; 1500 matrices exceed the 1024 wavefronts resident on the chip, so
+    each wavefront's loop over matrices runs more than once.  Sampled
+    matrices match the oracle's pivots exactly and its factors within
+    rounding."""
+    n, B = 100, 1500
+    rng = np.random.default_rng(1500)
+    A = rng.standard_normal((B, n, n))
+    LU, piv, info = gpu.lu_factor_batch(dev(A.copy()))
+    LU, piv, info = LU.cpu().numpy(), piv.cpu().numpy(), info.cpu().numpy()
+    assert np.all(info == 0)
+    for b in list(range(0, B, 97)) + [B - 1]:
+        lo, po, io = oracle_mod.lu_factor(A[b])
+        np.testing.assert_array_equal(piv[b], po)
+        np.testing.assert_allclose(LU[b], lo, rtol=1e-10, atol=1e-12 * np.abs(A[b]).max())
+
+
+def test_lu_fp64_wavefront_kernel_singular_info(gpu):
+    """info of the first zero pivot column on the wavefront kernel: a zero
+    on the diagonal of an identity at column 50, and an all-zero matrix."""
+    n = 101
+    A = np.zeros((2, n, n))
+    A[0] = np.eye(n)
+    A[0, 50, 50] = 0.0
+    _, _, info = gpu.lu_factor_batch(dev(A))
+    assert info.cpu().numpy().tolist() == [51, 1]
 
 
 def test_lu_singular_info(gpu):
