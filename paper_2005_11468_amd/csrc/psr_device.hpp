@@ -118,14 +118,18 @@ struct Layout {
   int kf, kr, Rf, Rr, sumC, dqdT, dqdC;               // reaction scratch
   int soot;                                           // soot-closure scratch (n = N + 7 only)
   int red, total;
-  __host__ __device__ void make(int N_, int I_, int n_, bool mixed, int BS, bool split_ = false) {
+  // lean: a residual evaluation alone (x, G and the residual's scratch; the
+  // solver vectors, the Jacobian scratch and the matrices get no space)
+  __host__ __device__ void make(int N_, int I_, int n_, bool mixed, int BS, bool split_ = false, bool lean = false) {
     N = N_; I = I_; n = n_;
     lda = (n % 2 == 0) ? n + 1 : n;
-    split = split_ ? 1 : 0;
+    split = (split_ || lean) ? 1 : 0;
+    const int nv = lean ? 0 : n;  // size of a solver vector
     int o = 0;
     Yin = o; o += N; Hin = o; o += N;
-    x = o; o += n; xnw = o; o += n; xev = o; o += n; d = o; o += n; t = o; o += n;
-    M = o; o += n; G = o; o += n; rs = o; o += n; cs = o; o += n; rb = o; o += n; rr = o; o += n;
+    x = o; o += n; G = o; o += n;
+    xnw = o; o += nv; xev = o; o += nv; d = o; o += nv; t = o; o += nv;
+    M = o; o += nv; rs = o; o += nv; cs = o; o += nv; rb = o; o += nv; rr = o; o += nv;
     int m = split ? 0 : o;  // matrices follow the vectors, or start their own area
     A64 = m; m += n * lda;
     A32 = m; m += mixed ? (n * lda + 1) / 2 : 0;
@@ -134,9 +138,9 @@ struct Layout {
     else { mat_total = 0; o = m; }
     persist = o;
     C = o; o += N; hRT = o; o += N; sR = o; o += N; cpR = o; o += N; wdot = o; o += N;
-    gross = o; o += N; Erow = o; o += N; dwdT = o; o += N;
+    gross = o; o += N; Erow = o; o += lean ? 0 : N; dwdT = o; o += lean ? 0 : N;
     kf = o; o += I; kr = o; o += I; Rf = o; o += I; Rr = o; o += I;
-    sumC = o; o += I; dqdT = o; o += I; dqdC = o; o += 6 * I;
+    sumC = o; o += lean ? 0 : I; dqdT = o; o += lean ? 0 : I; dqdC = o; o += lean ? 0 : 6 * I;
     soot = o; o += (n == N + 7) ? kSootScratch : 0;
     red = o; o += BS + 8;
     total = o;

@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(kBS) k_residual(MechDev m, int energy, int64_t
   extern __shared__ double lds[];
   const int64_t b = xcd_reactor(blockIdx.x, gridDim.x);
   Layout L;
-  L.make(m.N, m.I, n_unknowns(m, energy), false, kBS, true);  // no matrix needed
+  L.make(m.N, m.I, n_unknowns(m, energy), false, kBS, true, true);  // a residual alone
   Ctx c = make_ctx(m, L, energy, P[b], tau[b], Tin[b], lds);
   load_inlet<kBS>(c, Yin, B, b);
   double *xl = c.p(L.x), *G = c.p(L.G);
@@ -953,9 +953,9 @@ static psr_status check_cond(psr_mech_t m, const psr_conditions *c) {
   return PSR_OK;
 }
 
-static size_t layout_bytes(psr_mech_t m, int energy, bool mixed, bool split = false) {
+static size_t layout_bytes(psr_mech_t m, int energy, bool mixed, bool split = false, bool lean = false) {
   Layout L;
-  L.make(m->N, m->I, n_unknowns(m->dev, energy), mixed, kBS, split);
+  L.make(m->N, m->I, n_unknowns(m->dev, energy), mixed, kBS, split, lean);
   return (size_t)L.total * 8;
 }
 
@@ -1014,7 +1014,7 @@ extern "C" psr_status psr_residual(psr_mech_t m, const psr_conditions *c, const 
       return PSR_OK;
     }
   }
-  const size_t lds = layout_bytes(m, c->energy, false, true);
+  const size_t lds = layout_bytes(m, c->energy, false, true, true);
   if (lds > (size_t)lds_limit_bytes()) return fail(PSR_EUNSUPPORTED, "mechanism too large for LDS");
   hipLaunchKernelGGL(k_residual, dim3((unsigned)c->n_reactors), dim3(kBS), lds, (hipStream_t)stream,
                      m->dev, c->energy, c->n_reactors, c->P, c->tau, c->T_in, c->Y_in, x, F,
