@@ -105,9 +105,14 @@ __device__ __forceinline__ void lds_order() { asm volatile("" ::: "memory"); }
 
 // Element (r, c) of the matrix being factored: the caller's double matrix
 // before the first panel has written the working copy, the copy after.
+// The caller's matrix is read once and written once: streaming accesses,
+// which leave the caches to the working copies.
+__device__ __forceinline__ double ld_once(const double *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void st_once(double v, double *p) { __builtin_nontemporal_store(v, p); }
+
 template <typename T, bool FIRST>
 __device__ __forceinline__ T ld_elem(const double *g, const T *M, int n, int ld, int r, int c) {
-  return FIRST ? (T)g[(int64_t)r * n + c] : M[(int64_t)r * ld + c];
+  return FIRST ? (T)ld_once(g + (int64_t)r * n + c) : M[(int64_t)r * ld + c];
 }
 
 // Pivot of column jj among the rows this lane holds (logical rows pos[j],
@@ -183,7 +188,7 @@ __device__ __forceinline__ void trailing(int n, int ld, int k0, int kb, int R0, 
       const int col = R0 + 16 * t + lr;
 #pragma unroll
       for (int v = 0; v < 4; v++)
-        c[t][v] = FIRST ? (T)g[(int64_t)(pr[v] < n ? pr[v] : n - 1) * n + (col < n ? col : n - 1)]
+        c[t][v] = FIRST ? (T)ld_once(g + (int64_t)(pr[v] < n ? pr[v] : n - 1) * n + (col < n ? col : n - 1))
                         : M[(int64_t)pr[v] * ld + col];
     }
   };
@@ -234,7 +239,7 @@ __device__ __forceinline__ void panel_step(int n, int ld, int k0, double *g, T *
       const double *src = g + (int64_t)phys[j] * n;  // n > 64: columns 0..15 exist
 #pragma unroll
       for (int c = 0; c < 16; c++) {
-        const T v = (T)src[c];
+        const T v = (T)ld_once(src + c);
         a[j][c] = ok ? v : (T)0;
       }
     } else if constexpr (sizeof(T) == 4) {
@@ -420,7 +425,7 @@ __device__ __forceinline__ int factor(int n, int ld, double *g, T *M, int *piv, 
 #pragma unroll
       for (int gq = 0; gq < GQ; gq++) {
         const int c = lane + 64 * gq;
-        if (i < n && c < n) g[(int64_t)i * n + c] = (double)v[r][gq];
+        if (i < n && c < n) st_once((double)v[r][gq], g + (int64_t)i * n + c);
       }
     }
   }

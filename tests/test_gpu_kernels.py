@@ -187,6 +187,24 @@ def test_lu_float_blocked_matrix_core(gpu, n, B):
         assert err <= bound, (b, err, bound)
 
 
+@pytest.mark.parametrize("n", [150, 201, 256])
+def test_lu_solve_large_matches_oracle(gpu, oracle_mod, n):
+    """Triangular solves for n above the FP64 factor range (the float factors
+    of the same call, stored as double) on the one-wavefront-per-matrix solve
+    kernel, all four right-hand-side slots of a lane in use at n = 256:
+    against the oracle's substitution with the same factors and pivots."""
+    rng = np.random.default_rng(1100 + n)
+    B = 5
+    A = rng.standard_normal((B, n, n))
+    LU, piv, info = gpu.lu_factor_batch(dev(A.copy()), precision=gpu.PSR_MIXED)
+    LU, piv = LU.cpu().numpy(), piv.cpu().numpy()
+    rhs = rng.standard_normal((B, n))
+    z = gpu.lu_solve_batch(dev(LU), dev(piv), dev(rhs.copy())).cpu().numpy()
+    for b in range(B):
+        zo = oracle_mod.lu_solve(LU[b], piv[b], rhs[b])
+        np.testing.assert_allclose(z[b], zo, rtol=1e-9, atol=1e-12 * np.abs(zo).max())
+
+
 def test_lu_float_blocked_singular_info(gpu):
     """A zero column after 70 elimination steps (second panel's interior) and
     an all-zero matrix: info = k + 1 of the first zero pivot column."""
