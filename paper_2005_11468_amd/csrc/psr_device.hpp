@@ -1179,6 +1179,12 @@ __device__ __forceinline__ int lu_factor_blocked64(double *A, int n, int lda, in
 
 template <int BS, typename T>
 __device__ void lu_solve(const T *A, int n, int lda, const int *piv, double *b) {
+  // Column-oriented substitution taken 16 columns at a time: the block's own
+  // 16 rows by the first wavefront (column by column, the finished element
+  // passed by readlane), then every other row by all threads, each applying
+  // the block's columns in order.  Every element receives the same updates in
+  // the same order as one column at a time would give it, with two block
+  // barriers per 16 columns instead of two per column.
   const int tid = threadIdx.x;
   if (tid == 0)
     for (int k = 0; k < n; k++) {
@@ -1187,16 +1193,61 @@ __device__ void lu_solve(const T *A, int n, int lda, const int *piv, double *b) 
       b[piv[k]] = t;
     }
   __syncthreads();
-  for (int k = 0; k < n - 1; k++) {
-    const double bk = b[k];
-    for (int i = k + 1 + tid; i < n; i += BS) b[i] -= (double)A[(int64_t)i * lda + k] * bk;
+  for (int k0 = 0; k0 < n - 1; k0 += 16) {  // forward, unit lower
+    const int k1 = k0 + 16 < n ? k0 + 16 : n;
+    if (tid < 64) {
+      const int i = k0 + tid;
+      const bool mine = tid < 16 && i < k1;
+      double zi = mine ? b[i] : 0.0;
+      double r[16];  // this lane's row of the block, loaded up front
+#pragma unroll
+      for (int kk = 0; kk < 16; kk++) r[kk] = (mine && k0 + kk < k1) ? (double)A[(int64_t)i * lda + k0 + kk] : 0.0;
+#pragma unroll
+      for (int kk = 0; kk < 15; kk++) {
+        if (k0 + kk < k1 - 1) {
+          const double bk = lane_read(zi, kk);
+          if (mine && tid > kk) zi -= r[kk] * bk;
+        }
+      }
+      if (mine) b[i] = zi;
+    }
+    __syncthreads();
+    for (int i = k1 + tid; i < n; i += BS) {
+      double zi = b[i];
+#pragma unroll
+      for (int kk = 0; kk < 16; kk++)
+        if (k0 + kk < k1) zi -= (double)A[(int64_t)i * lda + k0 + kk] * b[k0 + kk];
+      b[i] = zi;
+    }
     __syncthreads();
   }
-  for (int k = n - 1; k >= 0; k--) {
-    const double bk = b[k] / (double)A[(int64_t)k * lda + k];
+  for (int k1 = n; k1 > 0; k1 -= 16) {  // back, upper
+    const int k0 = k1 - 16 > 0 ? k1 - 16 : 0;
+    if (tid < 64) {
+      const int i = k0 + tid;
+      const bool mine = tid < 16 && i < k1;
+      double zi = mine ? b[i] : 0.0;
+      double r[16];  // this lane's row of the block, loaded up front
+#pragma unroll
+      for (int kk = 0; kk < 16; kk++) r[kk] = (mine && k0 + kk < k1) ? (double)A[(int64_t)i * lda + k0 + kk] : 0.0;
+#pragma unroll
+      for (int kk = 15; kk >= 0; kk--) {
+        if (k0 + kk < k1) {
+          const double bk = lane_read(zi, kk) / lane_read(r[kk], kk);
+          if (tid == kk) zi = bk;
+          else if (mine && tid < kk) zi -= r[kk] * bk;
+        }
+      }
+      if (mine) b[i] = zi;
+    }
     __syncthreads();
-    if (tid == 0) b[k] = bk;
-    for (int i = tid; i < k; i += BS) b[i] -= (double)A[(int64_t)i * lda + k] * bk;
+    for (int i = tid; i < k0; i += BS) {
+      double zi = b[i];
+#pragma unroll
+      for (int kk = 15; kk >= 0; kk--)
+        if (k0 + kk < k1) zi -= (double)A[(int64_t)i * lda + k0 + kk] * b[k0 + kk];
+      b[i] = zi;
+    }
     __syncthreads();
   }
 }
