@@ -208,7 +208,10 @@ psr_status psr_lu_factor_batch(int32_t n, int64_t batch, int32_t precision, doub
                                int32_t *info, void *stream);
 
 /* Solve with the factors of psr_lu_factor_batch: b (device [B][n]) is
- * overwritten with the solution.  Asynchronous.                            */
+ * overwritten with the solution (interchanges in order, then forward and
+ * back substitution; one wavefront per matrix).  Asynchronous.  n <= 256;
+ * larger n returns PSR_EUNSUPPORTED, null pointers or n, B <= 0
+ * PSR_EINVAL.                                                              */
 psr_status psr_lu_solve_batch(int32_t n, int64_t batch, const double *LU, const int32_t *piv,
                               double *b, void *stream);
 
