@@ -103,13 +103,13 @@ __device__ __forceinline__ void wave_fence() {
 // LDS writes and other lanes' reads only the compiler must keep the order.
 __device__ __forceinline__ void lds_order() { asm volatile("" ::: "memory"); }
 
-// Element (r, c) of the matrix being factored: the caller's double matrix
-// before the first panel has written the working copy, the copy after.
 // The caller's matrix is read once and written once: streaming accesses,
 // which leave the caches to the working copies.
 __device__ __forceinline__ double ld_once(const double *p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ void st_once(double v, double *p) { __builtin_nontemporal_store(v, p); }
 
+// Element (r, c) of the matrix being factored: the caller's double matrix
+// before the first panel has written the working copy, the copy after.
 template <typename T, bool FIRST>
 __device__ __forceinline__ T ld_elem(const double *g, const T *M, int n, int ld, int r, int c) {
   return FIRST ? (T)ld_once(g + (int64_t)r * n + c) : M[(int64_t)r * ld + c];
@@ -164,9 +164,13 @@ __device__ __forceinline__ void pivot<double, 2>(const double (&a)[2][16], int j
   }
 }
 
-// One panel step at column k0: factor columns k0..k0+kb-1 of the logical rows
-// k0..n-1, then U12 and the trailing update.  Loads are unconditional at
-// clamped in-range addresses, so the compiler can issue them together.
+// A22 -= L21 U12 for the trailing block at logical row and column R0 (a
+// multiple of 16), NT x NT tiles of 16: one row of tiles at a time in the
+// MFMA result layout, the loads of the next row issued before the products of
+// the current one.  Tiles reaching past n read and write the padding rows and
+// columns of the working copy, so no access is predicated; the zero rows of
+// the A operand and zero columns of U12 keep the padding out of the real
+// elements.
 template <typename T, int NT, bool FIRST>
 __device__ __forceinline__ void trailing(int n, int ld, int k0, int kb, int R0, const double *g, T *M,
                                          const WaveLds<T> &S, int lane) {
@@ -219,6 +223,9 @@ __device__ __forceinline__ void trailing(int n, int ld, int k0, int kb, int R0, 
   }
 }
 
+// One panel step at column k0: factor columns k0..k0+kb-1 of the logical rows
+// k0..n-1, then U12 and the trailing update.  Loads are unconditional at
+// clamped in-range addresses, so the compiler can issue them together.
 template <typename T, bool FIRST>
 __device__ __forceinline__ void panel_step(int n, int ld, int k0, double *g, T *M, int *piv, WaveLds<T> &S, int lane,
                                            int &info) {
