@@ -83,36 +83,30 @@ __device__ inline int matrix_finite(const double *A, int n, int lda, double *red
 template <int BS>
 __device__ void equilibration_scales(const Ctx &c, const double *A64, double *rs, double *cs) {
   const int n = c.n, lda = c.L.lda;
-  // four running maxima per thread keep four loads in flight (a maximum is
+  // eight running maxima per thread keep eight loads in flight (a maximum is
   // exact, so the order does not change the result)
   for (int i = threadIdx.x; i < n; i += BS) {
     const double *row = A64 + (int64_t)i * lda;
-    double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
+    double m[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int j = 0;
-    for (; j + 3 < n; j += 4) {
-      m0 = fmax(m0, fabs(row[j]));
-      m1 = fmax(m1, fabs(row[j + 1]));
-      m2 = fmax(m2, fabs(row[j + 2]));
-      m3 = fmax(m3, fabs(row[j + 3]));
-    }
-    for (; j < n; j++) m0 = fmax(m0, fabs(row[j]));
-    const double mx = fmax(fmax(m0, m1), fmax(m2, m3));
+    for (; j + 7 < n; j += 8)
+#pragma unroll
+      for (int u = 0; u < 8; u++) m[u] = fmax(m[u], fabs(row[j + u]));
+    for (; j < n; j++) m[0] = fmax(m[0], fabs(row[j]));
+    const double mx = fmax(fmax(fmax(m[0], m[1]), fmax(m[2], m[3])), fmax(fmax(m[4], m[5]), fmax(m[6], m[7])));
     int e = 0;
     if (mx > 0.0 && isfinite(mx)) frexp(mx, &e);
     rs[i] = ldexp(1.0, -e);
   }
   __syncthreads();
   for (int j = threadIdx.x; j < n; j += BS) {
-    double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
+    double m[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int i = 0;
-    for (; i + 3 < n; i += 4) {
-      m0 = fmax(m0, fabs(A64[(int64_t)i * lda + j] * rs[i]));
-      m1 = fmax(m1, fabs(A64[(int64_t)(i + 1) * lda + j] * rs[i + 1]));
-      m2 = fmax(m2, fabs(A64[(int64_t)(i + 2) * lda + j] * rs[i + 2]));
-      m3 = fmax(m3, fabs(A64[(int64_t)(i + 3) * lda + j] * rs[i + 3]));
-    }
-    for (; i < n; i++) m0 = fmax(m0, fabs(A64[(int64_t)i * lda + j] * rs[i]));
-    const double mx = fmax(fmax(m0, m1), fmax(m2, m3));
+    for (; i + 7 < n; i += 8)
+#pragma unroll
+      for (int u = 0; u < 8; u++) m[u] = fmax(m[u], fabs(A64[(int64_t)(i + u) * lda + j] * rs[i + u]));
+    for (; i < n; i++) m[0] = fmax(m[0], fabs(A64[(int64_t)i * lda + j] * rs[i]));
+    const double mx = fmax(fmax(fmax(m[0], m[1]), fmax(m[2], m[3])), fmax(fmax(m[4], m[5]), fmax(m[6], m[7])));
     int e = 0;
     if (mx > 0.0 && isfinite(mx)) frexp(mx, &e);
     cs[j] = ldexp(1.0, -e);
