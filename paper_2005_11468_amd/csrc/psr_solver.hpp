@@ -122,7 +122,21 @@ __device__ int factor_mixed(const Ctx &c, const double *A64, float *A32, int *pi
                             double *cs, double *red) {
   const int n = c.n, lda = c.L.lda;
   equilibration_scales<BS>(c, A64, rs, cs);
-  for (int e = threadIdx.x; e < n * n; e += BS) {
+  // four elements per pass, their loads issued together
+  int e = threadIdx.x;
+  for (; e + 3 * BS < n * n; e += 4 * BS) {
+    int64_t off[4];
+    float v[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int ee = e + u * BS, i = ee / n, j = ee % n;
+      off[u] = (int64_t)i * lda + j;
+      v[u] = (float)(A64[off[u]] * rs[i] * cs[j]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) A32[off[u]] = v[u];
+  }
+  for (; e < n * n; e += BS) {
     const int i = e / n, j = e % n;
     A32[(int64_t)i * lda + j] = (float)(A64[(int64_t)i * lda + j] * rs[i] * cs[j]);
   }
@@ -143,7 +157,21 @@ __device__ inline int factor64(const Ctx &c, double *A64, int *piv, double *red)
   const int n = c.n, lda = c.L.lda;
   double *rs = c.p(c.L.rs), *cs = c.p(c.L.cs);
   equilibration_scales<BS>(c, A64, rs, cs);
-  for (int e = threadIdx.x; e < n * n; e += BS) {
+  // four elements per pass, their loads issued together
+  int e = threadIdx.x;
+  for (; e + 3 * BS < n * n; e += 4 * BS) {
+    int64_t off[4];
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int ee = e + u * BS, i = ee / n, j = ee % n;
+      off[u] = (int64_t)i * lda + j;
+      v[u] = A64[off[u]] * (rs[i] * cs[j]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) A64[off[u]] = v[u];
+  }
+  for (; e < n * n; e += BS) {
     const int i = e / n, j = e % n;
     A64[(int64_t)i * lda + j] *= rs[i] * cs[j];
   }
