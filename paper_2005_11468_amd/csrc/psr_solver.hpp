@@ -69,7 +69,18 @@ __device__ inline int all_finite(const double *v, int n, double *red) {
 template <int BS>
 __device__ inline int matrix_finite(const double *A, int n, int lda, double *red) {
   int bad = 0;
-  for (int e = threadIdx.x; e < n * n; e += BS) bad |= !isfinite(A[(e / n) * lda + (e % n)]);
+  int e = threadIdx.x;
+  for (; e + 3 * BS < n * n; e += 4 * BS) {  // four loads in flight
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int ee = e + u * BS;
+      v[u] = A[(ee / n) * lda + (ee % n)];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) bad |= !isfinite(v[u]);
+  }
+  for (; e < n * n; e += BS) bad |= !isfinite(A[(e / n) * lda + (e % n)]);
   return !block_or<BS>(bad, red);
 }
 
